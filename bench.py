@@ -1,0 +1,205 @@
+"""Benchmark of the fused VP-LBM step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+
+A "step" is one lattice update of the whole grid: pull-streaming, edge rules, mask fetch,
+moments, penalization, collision, store, and the FP64 mass/force reductions.  The default
+workload is the 2048 x 512 cylinder wake (VP-MRT, FP32 storage, Zou-He inlet, outflow, free-slip
+walls, disk D = 64, Re = 200).  Its two population buffers (75 MB) fit in the 256 MB Infinity
+Cache, so the line also carries `hbm_resident`: the 8192 x 2048 oscillating-cylinder workload
+(FP32, mask rebuilt every step), whose buffers (1.2 GB) do not, and `reduced_precision`: the
+8192 x 2048 cylinder in FP16/BF16 storage shifted by the lattice weights.
+
+Prints one JSON line.  Inputs are synthetic (seeded geometry, uniform start) and resident on the
+GPU before timing starts.  `--copy-probe BYTES` instead times a plain device copy (the measured
+HBM ceiling and the calibration kernel for the FETCH_SIZE/WRITE_SIZE counters).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + % HBM roofline (D2Q9 VP-MRT step); served p50/p99 time-to-result"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E datasheet peak
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "lattice.hpp", "kernels.hpp", "runtime.hip"):
+        with open(os.path.join(ROOT, "paper_1812_05401_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, storage):
+    """HBM bytes per step-kernel launch from the committed counter summary, if it was taken on
+    the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    ent = tab.get(f"{workload}/{storage}")
+    if not ent or ent.get("source_digest") != source_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_workload(case, steps, warmup, storage=None):
+    import torch
+    from paper_1812_05401_amd import binding as B
+    if storage:
+        case.storage = storage
+    # A non-default torch stream: its handle is what the library orders its work on and what
+    # the timing events are recorded on (the default stream's handle is NULL, which the C ABI
+    # reads as "use a stream of your own").
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    sim = B.Simulation(case, stream=int(stream.cuda_stream))
+    assert sim.stream == stream.cuda_stream
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    obs = sim.observables()
+    sim.close()
+    if obs["status"] != 0:
+        raise RuntimeError(f"{case.name}: unstable")
+    bpu = B.vplbm_bytes_per_update(case.storage)
+    per_step_s = gpu_ms / 1e3 / steps
+    achieved = bpu * case.nodes / per_step_s / 1e9
+    traffic = measured_traffic(case.name, case.storage)
+    return {
+        "workload": case.name, "nx": case.nx, "ny": case.ny, "storage": case.storage,
+        "collision": case.collision, "steps": steps,
+        "mlups": case.nodes * steps / (gpu_ms / 1e3) / 1e6,
+        "ms_per_step": gpu_ms / steps, "wall_s": wall, "mass": obs["mass"],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_update": bpu,
+                     "kernel": "vplbm::step_kernel"},
+    }
+
+
+def cpu_baseline(case, steps):
+    import oracle as O
+    kinds = {"disk": O.DISK, "rect": O.RECT, "disk_outside": O.DISK_OUTSIDE}
+    bcs = {"periodic": O.PERIODIC, "velocity": O.VELOCITY, "outflow": O.OUTFLOW,
+           "freeslip": O.FREESLIP}
+    s = O.OracleSim(case.nx, case.ny, O.MRT if case.collision == "mrt" else O.SRT, tau=case.tau,
+                    lam=case.lam, eta=case.eta, bc=tuple(bcs[b] for b in case.bc), u_in=case.u_in)
+    s.set_bodies([O.make_body(kinds[b["kind"]], b["cx"], b["cy"], b["r"], b["hx"], b["hy"],
+                              b["ux"], b["uy"], b["omega"], b["ax"], b["ay"], b["freq"])
+                  for b in case.bodies])
+    s.init_uniform(case.rho0, *case.u0)
+    t0 = time.perf_counter()
+    s.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(case.nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} steps of {case.name} ({case.nodes} nodes), FP64 oracle, "
+                      f"{case.collision.upper()} in moment space, one thread, {dt:.1f} s"}
+
+
+def copy_probe(nbytes, reps):
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes": 4 * n, "reps": reps, "ms_per_copy": ms,
+                      "gbs_read_plus_write": 2 * 4 * n / (ms / 1e3) / 1e9}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--warmup", type=int, default=600)
+    ap.add_argument("--workload", default="cylinder_wake_2048x512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 8192 x 2048 objects")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for "
+              f"--gpus {args.gpus}).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, max(args.steps, 1))
+        return
+
+    from paper_1812_05401_amd import binding as B
+    from paper_1812_05401_amd import inputs as I
+    B.load()
+    workloads = {
+        "cylinder_wake_2048x512": I.cylinder_wake_2048x512,
+        "taylor_couette_128": I.taylor_couette_128,
+        "oscillating_cylinder_8192x2048": I.oscillating_cylinder_8192x2048,
+        "cylinder_wake_8192x2048": lambda: I.cylinder_wake_8192x2048("f32"),
+    }
+    case = workloads[args.workload]()
+    main_res = time_workload(case, args.steps, args.warmup)
+    print(f"# {case.name}: {main_res['mlups']:.0f} MLUPS, {main_res['ms_per_step'] * 1e3:.2f} us/step",
+          file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC, "value": round(main_res["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16s": "f16", "bf16s": "bf16"}[case.storage],
+        "data": "synthetic",
+        "config": {"workload": case.name, "nx": case.nx, "ny": case.ny,
+                   "collision": case.collision, "storage": case.storage, "tau": case.tau,
+                   "lambda": case.lam, "eta": case.eta, "bc": list(case.bc),
+                   "bodies": len(case.bodies), "reductions": "fp64 mass + body force, every step",
+                   "cache_resident": case.nx * case.ny * 2 * 9 * {"f64": 8, "f32": 4}.get(case.storage, 2) < 256e6},
+        "roofline": main_res["roofline"],
+    }
+    if not args.no_extra:
+        big = I.oscillating_cylinder_8192x2048()
+        r = time_workload(big, 400, 40)
+        line["hbm_resident"] = {k: r[k] for k in ("workload", "storage", "mlups", "ms_per_step", "roofline")}
+        print(f"# {big.name}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        red = {}
+        for st in ("f32", "f16s", "bf16s"):
+            c = I.cylinder_wake_8192x2048(st)
+            r = time_workload(c, 400, 40)
+            red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "roofline")}
+            print(f"# {c.name}/{st}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        line["reduced_precision"] = {"workload": "cylinder_wake_8192x2048", **red}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(I.cylinder_wake_2048x512(), 40)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

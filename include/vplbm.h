@@ -1,0 +1,162 @@
+/*
+ * vplbm.h — C ABI of the MI355X (gfx950) volume-penalization lattice Boltzmann library.
+ *
+ * The operation: Benamour, Liberge & Beghein, "A volume penalization lattice Boltzmann method for
+ * simulating flows in the presence of obstacles" (arXiv:1812.05401), Section 2.  A D2Q9 lattice
+ * is advanced on every node, fluid and solid alike; obstacles enter only through the penalization
+ * body force f = -rho (chi/eta)(u - u_s) (Eq. 17), with the velocity solved implicitly (Eq. 18) and
+ * the force injected by the Guo term (SRT, Eqs. 2 and 7) or the Lu term (MRT, Eqs. 10-16).
+ *
+ * Conventions shared by every call:
+ *   - Lattice units, dx = dt = 1.  Node (x, y) sits at integer coordinates 0 <= x < nx, 0 <= y < ny.
+ *   - Directions alpha = 0..8 follow Eq. 3: 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
+ *   - Host arrays are row-major, x fastest: field[y*nx + x]; populations pop[(a*ny + y)*nx + x].
+ *   - Every host pointer is owned by the caller and only read or written during the call (or,
+ *     for asynchronous calls, copied before the call returns).  The library owns all device memory.
+ *   - Every call returns 0 (VPLBM_OK) or a negative error code; vplbm_last_error() then holds a
+ *     message for the calling thread.  No C++ exception crosses the ABI.
+ *   - A handle is not thread-safe: use one handle per thread or lock around calls.
+ *   - The stored state is the post-collision population.  Step n (n = 0, 1, ...) streams it,
+ *     applies the edge rules, computes the moments and the penalized velocity, collides and stores;
+ *     bodies are placed at time t = n during step n.
+ */
+#ifndef VPLBM_H
+#define VPLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VPLBM_ABI_VERSION 1
+#define VPLBM_MAX_BODIES 8
+/* doubles per step in the observable ring: mass, then (fx, fy) for each of the 8 bodies */
+#define VPLBM_RING_WIDTH (1 + 2 * VPLBM_MAX_BODIES)
+
+enum vplbm_error {
+    VPLBM_OK = 0,
+    VPLBM_EINVAL = -1,     /* bad argument, bad configuration, NULL or destroyed handle */
+    VPLBM_ENOMEM = -2,     /* device or host allocation failed */
+    VPLBM_EHIP = -3,       /* a HIP runtime call failed (message has the HIP error string) */
+    VPLBM_EUNSTABLE = -4,  /* the simulation produced a non-finite or non-positive density */
+    VPLBM_EBUDGET = -5,    /* a pool request can never fit the pool's memory budget */
+    VPLBM_ESTATE = -6      /* the call is not valid in the object's current state */
+};
+
+/* Collision (Section 2.1).  VPLBM_MRT uses the rates of Eq. 14 with s_n = 1/tau and s_q from
+   Lambda (Eq. 15); VPLBM_SRT is the single rate 1/tau with the Guo term (Eqs. 2, 7). */
+enum vplbm_collision { VPLBM_SRT = 0, VPLBM_MRT = 1 };
+
+/* Storage of the populations.  F64 and F32 store f.  F16S and BF16S store f - w_alpha (the
+   lattice weights of Eq. 5, i.e. the deviation from the rest state at rho = 1) rounded to nearest
+   even in binary16 / bfloat16; the collision then runs in FP32.  F64 computes in FP64. */
+enum vplbm_storage { VPLBM_F64 = 0, VPLBM_F32 = 1, VPLBM_F16S = 2, VPLBM_BF16S = 3 };
+
+/* Edge rules.  x edges: both PERIODIC, or VELOCITY (Zou-He inlet at x = 0 imposing (u_in_x,
+   u_in_y)) with OUTFLOW (zero-gradient outlet at x = nx-1).  y edges: both PERIODIC or both
+   FREESLIP (specular reflection, wall half a link outside the first and last rows). */
+enum vplbm_bc { VPLBM_PERIODIC = 0, VPLBM_VELOCITY = 1, VPLBM_OUTFLOW = 2, VPLBM_FREESLIP = 3 };
+
+/* Obstacle shapes; a node belongs to a body when its centre lies inside (boundary included).
+   DISK_OUTSIDE is the complement of a disk (|x - c| >= r), e.g. a fixed outer cylinder. */
+enum vplbm_shape { VPLBM_DISK = 0, VPLBM_RECT = 1, VPLBM_DISK_OUTSIDE = 2 };
+
+typedef struct {
+    uint32_t abi_version;        /* must be VPLBM_ABI_VERSION */
+    int32_t nx, ny;              /* lattice size, 3 <= nx, ny and nx * ny < 2^31 */
+    int32_t collision;           /* enum vplbm_collision */
+    int32_t storage;             /* enum vplbm_storage */
+    double tau;                  /* relaxation time, > 1/2; viscosity nu = (tau - 1/2)/3 (Eq. 6) */
+    double lambda;               /* MRT: Lambda of Eq. 15 (> 0); ignored for SRT */
+    double eta;                  /* penalization parameter of Eq. 17, > 0 (the paper uses 1e-7) */
+    double rho0, ux0, uy0;       /* uniform initial state: f = f^eq(rho0, u0) (u_s inside bodies) */
+    int32_t bc_xlo, bc_xhi, bc_ylo, bc_yhi;   /* enum vplbm_bc */
+    double u_in_x, u_in_y;       /* inlet velocity for bc_xlo = VPLBM_VELOCITY, |u_in_x| < 1 */
+    int32_t reduce;              /* 1: per-step FP64 mass and body-force reductions; 0: none */
+    int32_t ring;                /* steps kept in the observable ring (0: 4096) */
+    void *stream;                /* hipStream_t the work is ordered on (e.g. torch's current
+                                    stream); NULL: a stream owned by the handle */
+} vplbm_config;
+
+typedef struct {
+    int32_t kind;                /* enum vplbm_shape */
+    double cx, cy;               /* centre at t = 0 */
+    double r;                    /* radius (DISK, DISK_OUTSIDE) */
+    double hx, hy;               /* half-sides (RECT) */
+    double ux, uy, omega;        /* rigid velocity: u_s(x) = U + omega e_z x (x - c(t)) */
+    double ax, ay, freq;         /* prescribed motion c(t) = c0 + a sin(2 pi freq t); adds
+                                    a 2 pi freq cos(2 pi freq t) to U.  Needs device masks. */
+} vplbm_body;
+
+typedef struct {
+    int64_t step;                /* index of the last executed step, -1 before the first */
+    double mass;                 /* sum of rho over all nodes in that step (reduce = 1) */
+    double fx[VPLBM_MAX_BODIES]; /* force of the fluid on body k: minus the sum of the     */
+    double fy[VPLBM_MAX_BODIES]; /* penalization force over the body's nodes in that step  */
+    int32_t nbodies;
+    int32_t status;              /* 0 ok, 1 unstable (non-finite or non-positive density seen) */
+} vplbm_obs;
+
+typedef struct vplbm_sim_s *vplbm_sim;
+
+/* Create a simulation: validates cfg, allocates the two population buffers, the mask and the
+   observable ring on the device, and sets f = f^eq(rho0, u0) everywhere (no bodies yet).
+   Work is ordered on cfg->stream.  On error *out is NULL. */
+int vplbm_create(const vplbm_config *cfg, vplbm_sim *out);
+
+/* Set the obstacles (Section 2.2: chi and u_s).  bodies[0..nbodies) (nbodies <= 8) give the
+   solid velocity of body k; body_id, if not NULL, is a host nx*ny plane with 0 = fluid and
+   k = bodies[k-1], copied in; if NULL the mask is rasterized on the device from the shapes (the
+   lowest-index body owns a node) and, for moving bodies, rebuilt before every step.  A moving
+   body requires body_id == NULL.  Before the first step this also resets the populations to the
+   uniform initial state with u_s inside the bodies.  Stream-ordered. */
+int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies, int32_t nbodies);
+
+/* Advance nsteps >= 0 steps (asynchronous on the stream).  Chunks of steps are replayed from a
+   captured HIP graph.  Returns VPLBM_EUNSTABLE if an earlier vplbm_observables saw status 1. */
+int vplbm_step(vplbm_sim s, int64_t nsteps);
+
+/* Observables of the last executed step; if rho/ux/uy are not NULL they receive (host, nx*ny,
+   FP64) the density and penalized velocity (Eqs. 8, 9, 18) of the current state, i.e. the
+   moments the next step computes.  Synchronizes the stream. */
+int vplbm_observables(vplbm_sim s, vplbm_obs *out, double *rho, double *ux, double *uy);
+
+/* Destroy the handle and free its device memory.  NULL-safe.  Synchronizes the stream. */
+int vplbm_destroy(vplbm_sim s);
+
+/* Message for the last error on the calling thread ("" if none).  Valid until the next call. */
+const char *vplbm_last_error(void);
+
+/* ---- extensions ------------------------------------------------------------------------- */
+
+/* Set f = f^eq(rho, u) per node from host FP64 fields (nx*ny each).  Stream-ordered. */
+int vplbm_init_fields(vplbm_sim s, const double *rho, const double *ux, const double *uy);
+
+/* Copy the populations to / from a host FP64 array [9][ny][nx] (decoded from / encoded to the
+   storage format).  set also sets the step counter to `step` (checkpoint/resume).  Both
+   synchronize the stream. */
+int vplbm_get_populations(vplbm_sim s, double *pop);
+int vplbm_set_populations(vplbm_sim s, const double *pop, int64_t step);
+
+/* Copy the current body-id plane (host nx*ny).  Synchronizes. */
+int vplbm_get_mask(vplbm_sim s, uint8_t *body_id);
+
+/* Copy the per-step observables of steps [first, first+count) from the device ring into
+   out[count][VPLBM_RING_WIDTH] (mass, fx0, fy0, ..., fx7, fy7).  The steps must still be in the
+   ring (the last `ring` steps).  Synchronizes. */
+int vplbm_force_series(vplbm_sim s, int64_t first, int64_t count, double *out);
+
+/* Number of steps done and the handle's stream (hipStream_t). */
+int vplbm_steps_done(vplbm_sim s, int64_t *steps);
+int vplbm_stream(vplbm_sim s, void **stream);
+
+/* Algorithmic HBM bytes of one lattice update for a storage format: 9 population loads,
+   9 population stores and the 1-byte mask. */
+int vplbm_bytes_per_update(int32_t storage, int64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VPLBM_H */

@@ -1,0 +1,312 @@
+"""ctypes binding of the C ABI in include/vplbm.h (argument marshalling only).
+
+Every function here calls the HIP library ``libvplbm.so``; there is no other compute path.  If
+the library is missing, every call raises.  Function names follow the C entry points; the
+``Simulation`` class wraps one handle.
+
+Array conventions: fields are numpy ``[ny, nx]`` FP64 (x fastest); populations ``[9, ny, nx]``.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+ABI_VERSION = 1
+MAX_BODIES = 8
+RING_WIDTH = 1 + 2 * MAX_BODIES
+
+OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, EBUDGET, ESTATE = 0, -1, -2, -3, -4, -5, -6
+SRT, MRT = 0, 1
+F64, F32, F16S, BF16S = 0, 1, 2, 3
+PERIODIC, VELOCITY, OUTFLOW, FREESLIP = 0, 1, 2, 3
+DISK, RECT, DISK_OUTSIDE = 0, 1, 2
+
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
+COLLISION = {"srt": SRT, "mrt": MRT}
+BC = {"periodic": PERIODIC, "velocity": VELOCITY, "outflow": OUTFLOW, "freeslip": FREESLIP}
+SHAPE = {"disk": DISK, "rect": RECT, "disk_outside": DISK_OUTSIDE}
+
+
+class VplbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"vplbm error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32),
+                ("collision", C.c_int32), ("storage", C.c_int32), ("tau", C.c_double),
+                ("lambda_", C.c_double), ("eta", C.c_double), ("rho0", C.c_double),
+                ("ux0", C.c_double), ("uy0", C.c_double), ("bc_xlo", C.c_int32),
+                ("bc_xhi", C.c_int32), ("bc_ylo", C.c_int32), ("bc_yhi", C.c_int32),
+                ("u_in_x", C.c_double), ("u_in_y", C.c_double), ("reduce", C.c_int32),
+                ("ring", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Body(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("cx", C.c_double), ("cy", C.c_double), ("r", C.c_double),
+                ("hx", C.c_double), ("hy", C.c_double), ("ux", C.c_double), ("uy", C.c_double),
+                ("omega", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
+                ("freq", C.c_double)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("fx", C.c_double * MAX_BODIES),
+                ("fy", C.c_double * MAX_BODIES), ("nbodies", C.c_int32), ("status", C.c_int32)]
+
+
+# (name, restype, argtypes) of every entry point declared in include/vplbm.h
+_dp = C.POINTER(C.c_double)
+SIGNATURES = [
+    ("vplbm_create", C.c_int, [C.POINTER(Config), C.POINTER(C.c_void_p)]),
+    ("vplbm_set_mask", C.c_int, [C.c_void_p, C.POINTER(C.c_uint8), C.POINTER(Body), C.c_int32]),
+    ("vplbm_step", C.c_int, [C.c_void_p, C.c_int64]),
+    ("vplbm_observables", C.c_int, [C.c_void_p, C.POINTER(Obs), _dp, _dp, _dp]),
+    ("vplbm_destroy", C.c_int, [C.c_void_p]),
+    ("vplbm_last_error", C.c_char_p, []),
+    ("vplbm_init_fields", C.c_int, [C.c_void_p, _dp, _dp, _dp]),
+    ("vplbm_get_populations", C.c_int, [C.c_void_p, _dp]),
+    ("vplbm_set_populations", C.c_int, [C.c_void_p, _dp, C.c_int64]),
+    ("vplbm_get_mask", C.c_int, [C.c_void_p, C.POINTER(C.c_uint8)]),
+    ("vplbm_force_series", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, _dp]),
+    ("vplbm_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("vplbm_stream", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("vplbm_bytes_per_update", C.c_int, [C.c_int32, C.POINTER(C.c_int64)]),
+]
+
+_lib = None
+
+
+def library_path():
+    return _build.LIB
+
+
+def load():
+    """Load libvplbm.so (built in-tree by ``python -m paper_1812_05401_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise RuntimeError(f"{_build.LIB} is not built: run python -m paper_1812_05401_amd.build")
+        L = C.CDLL(_build.LIB)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error():
+    return load().vplbm_last_error().decode()
+
+
+def check(rc):
+    if rc != OK:
+        raise VplbmError(rc, last_error())
+    return rc
+
+
+def _ptr(a, ctype=C.c_double):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def torch_stream():
+    """hipStream_t of torch's current stream on the current device (torch owns the stream)."""
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def make_config(nx, ny, collision="mrt", storage="f32", tau=0.8, lam=3 / 16, eta=1e-7, rho0=1.0,
+                u0=(0.0, 0.0), bc=("periodic",) * 4, u_in=(0.0, 0.0), reduce=True, ring=0,
+                stream=None):
+    cfg = Config()
+    cfg.abi_version = ABI_VERSION
+    cfg.nx, cfg.ny = int(nx), int(ny)
+    cfg.collision = COLLISION.get(collision, collision)
+    cfg.storage = STORAGE.get(storage, storage)
+    cfg.tau, cfg.lambda_, cfg.eta = float(tau), float(lam), float(eta)
+    cfg.rho0, cfg.ux0, cfg.uy0 = float(rho0), float(u0[0]), float(u0[1])
+    cfg.bc_xlo, cfg.bc_xhi, cfg.bc_ylo, cfg.bc_yhi = (BC.get(b, b) for b in bc)
+    cfg.u_in_x, cfg.u_in_y = float(u_in[0]), float(u_in[1])
+    cfg.reduce = 1 if reduce else 0
+    cfg.ring = int(ring)
+    cfg.stream = stream
+    return cfg
+
+
+def make_body(b):
+    """vplbm_body from a dict with the keys of paper_1812_05401_amd.inputs.body."""
+    return Body(SHAPE.get(b["kind"], b["kind"]), b["cx"], b["cy"], b.get("r", 0.0), b.get("hx", 0.0),
+                b.get("hy", 0.0), b.get("ux", 0.0), b.get("uy", 0.0), b.get("omega", 0.0),
+                b.get("ax", 0.0), b.get("ay", 0.0), b.get("freq", 0.0))
+
+
+# ---- entry points ------------------------------------------------------------------------------
+
+def vplbm_create(cfg):
+    h = C.c_void_p()
+    check(load().vplbm_create(C.byref(cfg), C.byref(h)))
+    return h.value
+
+
+def vplbm_set_mask(h, body_id, bodies):
+    arr = (Body * max(1, len(bodies)))(*[make_body(b) if isinstance(b, dict) else b for b in bodies])
+    ids = None
+    if body_id is not None:
+        body_id = np.ascontiguousarray(body_id, dtype=np.uint8)
+        ids = _ptr(body_id, C.c_uint8)
+    check(load().vplbm_set_mask(h, ids, arr, len(bodies)))
+
+
+def vplbm_step(h, n):
+    check(load().vplbm_step(h, int(n)))
+
+
+def vplbm_observables(h, shape=None, fields=False):
+    o = Obs()
+    rho = ux = uy = None
+    ptrs = [None, None, None]
+    if fields:
+        ny, nx = shape
+        rho, ux, uy = (np.empty((ny, nx)) for _ in range(3))
+        ptrs = [_ptr(rho), _ptr(ux), _ptr(uy)]
+    check(load().vplbm_observables(h, C.byref(o), *ptrs))
+    nb = o.nbodies
+    obs = {"step": o.step, "mass": o.mass, "fx": np.array(o.fx[:nb]), "fy": np.array(o.fy[:nb]),
+           "status": o.status}
+    return (obs, rho, ux, uy) if fields else obs
+
+
+def vplbm_destroy(h):
+    check(load().vplbm_destroy(h))
+
+
+def vplbm_init_fields(h, rho, ux, uy):
+    rho, ux, uy = (np.ascontiguousarray(v, dtype=np.float64) for v in (rho, ux, uy))
+    check(load().vplbm_init_fields(h, _ptr(rho), _ptr(ux), _ptr(uy)))
+
+
+def vplbm_get_populations(h, shape):
+    ny, nx = shape
+    pop = np.empty((9, ny, nx))
+    check(load().vplbm_get_populations(h, _ptr(pop)))
+    return pop
+
+
+def vplbm_set_populations(h, pop, step):
+    pop = np.ascontiguousarray(pop, dtype=np.float64)
+    check(load().vplbm_set_populations(h, _ptr(pop), int(step)))
+
+
+def vplbm_get_mask(h, shape):
+    ids = np.empty(shape, dtype=np.uint8)
+    check(load().vplbm_get_mask(h, _ptr(ids, C.c_uint8)))
+    return ids
+
+
+def vplbm_force_series(h, first, count):
+    out = np.empty((count, RING_WIDTH))
+    check(load().vplbm_force_series(h, int(first), int(count), _ptr(out)))
+    return out
+
+
+def vplbm_steps_done(h):
+    n = C.c_int64()
+    check(load().vplbm_steps_done(h, C.byref(n)))
+    return n.value
+
+
+def vplbm_stream(h):
+    s = C.c_void_p()
+    check(load().vplbm_stream(h, C.byref(s)))
+    return s.value
+
+
+def vplbm_bytes_per_update(storage):
+    b = C.c_int64()
+    check(load().vplbm_bytes_per_update(STORAGE.get(storage, storage), C.byref(b)))
+    return b.value
+
+
+# ---- one handle ---------------------------------------------------------------------------------
+
+class Simulation:
+    """A simulation on the GPU.  ``case`` is a paper_1812_05401_amd.inputs.Case (or pass the
+    config fields as keywords).  ``stream``: hipStream_t as an int, 'torch' for torch's current
+    stream, or None for a stream owned by the library."""
+
+    def __init__(self, case=None, stream="torch", reduce=True, ring=0, device_mask=True, **kw):
+        if stream == "torch":
+            stream = torch_stream()
+        if case is not None:
+            kw = dict(nx=case.nx, ny=case.ny, collision=case.collision, storage=case.storage,
+                      tau=case.tau, lam=case.lam, eta=case.eta, rho0=case.rho0, u0=case.u0,
+                      bc=case.bc, u_in=case.u_in, **kw)
+        self.cfg = make_config(reduce=reduce, ring=ring, stream=stream, **kw)
+        self.nx, self.ny = self.cfg.nx, self.cfg.ny
+        self.h = vplbm_create(self.cfg)
+        self.nbodies = 0
+        if case is not None and case.bodies:
+            self.set_mask(None if device_mask else "host", case.bodies)
+
+    @property
+    def shape(self):
+        return (self.ny, self.nx)
+
+    def set_mask(self, body_id, bodies):
+        if isinstance(body_id, str):
+            raise ValueError("pass a body-id array or None")
+        vplbm_set_mask(self.h, body_id, bodies)
+        self.nbodies = len(bodies)
+
+    def step(self, n=1):
+        vplbm_step(self.h, n)
+
+    def observables(self, fields=False):
+        return vplbm_observables(self.h, self.shape, fields)
+
+    def fields(self):
+        _, rho, ux, uy = vplbm_observables(self.h, self.shape, True)
+        return rho, ux, uy
+
+    def init_fields(self, rho, ux, uy):
+        vplbm_init_fields(self.h, rho, ux, uy)
+
+    def populations(self):
+        return vplbm_get_populations(self.h, self.shape)
+
+    def set_populations(self, pop, step=0):
+        vplbm_set_populations(self.h, pop, step)
+
+    def mask(self):
+        return vplbm_get_mask(self.h, self.shape)
+
+    def force_series(self, first, count):
+        return vplbm_force_series(self.h, first, count)
+
+    @property
+    def steps_done(self):
+        return vplbm_steps_done(self.h)
+
+    @property
+    def stream(self):
+        return vplbm_stream(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            vplbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,82 @@
+// Kernel argument records and host-side launchers of the VP-LBM library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace vplbm {
+
+constexpr int kMaxBodies = 8;
+constexpr int kRingWidth = 1 + 2 * kMaxBodies;   // mass, (fx, fy) per body
+constexpr int kBlock = 256;                      // threads per workgroup (4 wave64)
+// Per-step reductions go through kSub sub-slots: workgroup b adds its partials into sub-slot
+// b % kSub, so no address takes more than 1/kSub of the atomics (device-scope FP64 atomics to
+// one address serialize).  The next step's first workgroup (or the fold kernel at observation
+// time) sums the sub-slots in a fixed order into the ring.
+constexpr int kSub = 64;
+
+struct BodyParams {          // as given by the caller (vplbm_body), device copy
+    int kind;                // 0 disk, 1 rect, 2 outside of a disk
+    double cx, cy, r, hx, hy, ux, uy, omega, ax, ay, freq;
+};
+
+// Everything one launch of the step kernel needs.  Passed by value (kernel arguments).
+struct StepArgs {
+    const void *src;         // post-collision planes of the previous step
+    void *dst;               // planes this step writes
+    const uint8_t *mask;     // body id per node (pitch = geometry pitch)
+    const BodyState *bodies; // body state at this step's time
+    double *ring;            // [ring_len][kRingWidth] per-step observables
+    double *acc;             // [2][kSub][kRingWidth] partial sums of the last two steps
+    unsigned *status;        // bit 0: non-finite or non-positive density seen
+    const long long *t_base; // step counter on the device
+    Geom g;
+    int t_off;               // this launch's step = *t_base + t_off
+    int ring_len;
+    int reduce;              // 1: accumulate mass and body forces into the ring
+    int ntx;                 // tiles along x
+    int bx_log2, by;         // workgroup = (1 << bx_log2) x by threads
+    int rows;                // each thread updates `rows` nodes, by rows apart
+    double sp, sm, kp, km;   // even/odd relaxation rates and 1 - s/2
+    double k_relax, c_pen;   // 1/(1 + 1/(2 eta)) and 1/(eta + 1/2)
+    double uin_x, uin_y;
+};
+
+struct TileShape {
+    int bx_log2, by, rows, ntx, nty;   // a tile is (1 << bx_log2) x (by * rows) nodes
+};
+TileShape tile_shape(int nx, int ny, int elem_bytes);
+
+hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st);
+
+// Per-node density and penalized velocity of the current state into dense FP64 arrays.
+hipError_t launch_readback(int storage, const StepArgs &a, double *rho, double *ux, double *uy,
+                           hipStream_t st);
+
+// f = f^eq(rho, u): from dense device fields (rho/ux/uy) if given, else (rho0, u0) with u_s in
+// solid nodes.
+hipError_t launch_init(int storage, const StepArgs &a, const double *rho, const double *ux,
+                       const double *uy, double rho0, double ux0, double uy0, hipStream_t st);
+
+// Dense FP64 [9][ny][nx] <-> the storage planes of a.dst (encode) / a.src (decode).
+hipError_t launch_encode(int storage, const StepArgs &a, const double *pop, hipStream_t st);
+hipError_t launch_decode(int storage, const StepArgs &a, double *pop, hipStream_t st);
+
+// Body states at time *t_base + t_off.
+hipError_t launch_bodies(const BodyParams *params, BodyState *state, int nbodies,
+                         const long long *t_base, int t_off, hipStream_t st);
+
+// Rasterize the bodies into the mask over the rectangle [x0, x0+w) x [y0, y0+h).
+hipError_t launch_mask(uint8_t *mask, const Geom &g, const BodyParams *params,
+                       const BodyState *state, int nbodies, int x0, int y0, int w, int h,
+                       hipStream_t st);
+
+hipError_t launch_advance(long long *t_base, long long n, hipStream_t st);
+// Sum the sub-slots of step *t_base - 1 into its ring entry (without clearing them).
+hipError_t launch_fold(const StepArgs &a, hipStream_t st);
+hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
+hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t st);
+
+}  // namespace vplbm

@@ -1,0 +1,262 @@
+// Per-node device code of the VP-LBM step (arXiv:1812.05401, Section 2) for gfx950.
+//
+// One node = pull 9 populations (left side of Eqs. 2/10), apply the edge rules, take the moments
+// (Eqs. 8-9), solve the penalized velocity and force (Eqs. 17-18), collide, store 9 populations.
+//
+// Collision.  Eq. 14 relaxes every even non-conserved moment (e, eps, p_xx, p_xy) with s_n and
+// both odd non-conserved moments (q_x, q_y) with s_q; the conserved moments come out the same for
+// any of their rates because the Lu term adds exactly the force to the momentum.  So the MRT of
+// Eqs. 10-16 is a two-relaxation-time collision: the symmetric half (f_a + f_abar)/2 of every
+// opposite pair relaxes with s+ = s_n, the antisymmetric half with s- = s_q, and the forcing term
+// splits as (1 - s+/2) F+ + (1 - s-/2) F-.  The SRT of Eqs. 2 and 7 is the case s+ = s- = 1/tau,
+// as the paper states for equal rates.  This form needs no 9x9 products.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vplbm {
+
+enum Storage { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+
+// ---- storage codecs --------------------------------------------------------------------------
+// F16S/BF16S keep h = f - w_a, so the stored numbers are the small deviations from rest and the
+// format's relative precision applies to them rather than to f.
+
+template <int S> struct Codec;
+
+template <> struct Codec<kF64> {
+    using elem = double;
+    using real = double;
+    static __device__ __forceinline__ real load(const elem *p, int i, real) { return p[i]; }
+    static __device__ __forceinline__ void store(elem *p, int i, real v, real) { p[i] = v; }
+};
+
+template <> struct Codec<kF32> {
+    using elem = float;
+    using real = float;
+    static __device__ __forceinline__ real load(const elem *p, int i, real) { return p[i]; }
+    static __device__ __forceinline__ void store(elem *p, int i, real v, real) { p[i] = v; }
+};
+
+template <> struct Codec<kF16S> {
+    using elem = _Float16;
+    using real = float;
+    static __device__ __forceinline__ real load(const elem *p, int i, real w) { return (float)p[i] + w; }
+    static __device__ __forceinline__ void store(elem *p, int i, real v, real w) { p[i] = (_Float16)(v - w); }
+};
+
+template <> struct Codec<kBF16S> {
+    using elem = __bf16;
+    using real = float;
+    static __device__ __forceinline__ real load(const elem *p, int i, real w) { return (float)p[i] + w; }
+    static __device__ __forceinline__ void store(elem *p, int i, real v, real w) { p[i] = (__bf16)(v - w); }
+};
+
+// Lattice weights of Eq. 5 in the compute type.
+template <typename T> struct W {
+    static constexpr T rest = T(4.0 / 9.0);
+    static constexpr T axis = T(1.0 / 9.0);
+    static constexpr T diag = T(1.0 / 36.0);
+};
+
+template <typename T> __device__ __forceinline__ T weight(int a)
+{
+    return a == 0 ? W<T>::rest : (a <= 4 ? W<T>::axis : W<T>::diag);
+}
+
+// ---- geometry and edges ------------------------------------------------------------------------
+
+struct Geom {
+    int nx, ny, pitch;      // pitch: elements per row (>= nx, multiple of 64)
+    int plane;              // elements per population plane
+    int xper, yper;         // periodic x / y
+    int inlet;              // Zou-He velocity inlet on x = 0 (then x = nx-1 is a zero-gradient outlet)
+};
+
+// Source of direction a at edge node (x, y) under the edge rules: a row outside the lattice
+// wraps (periodic) or is replaced by the specular image in the same row (free-slip: the
+// population arriving in a left with the y-mirrored direction); a column outside wraps
+// (periodic) or is clamped to the edge column (outlet; at the inlet it is a placeholder that
+// the inlet rule overwrites).  Mirroring keeps |xi|, so the lattice weight is unchanged.
+__device__ __forceinline__ int edge_source(int a, int x, int y, const Geom &g, int &plane_dir)
+{
+    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr int mirror_y[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+    int sx = x - cx[a], sy = y - cy[a];
+    plane_dir = a;
+    if (sy < 0 || sy >= g.ny) {
+        if (g.yper) sy += sy < 0 ? g.ny : -g.ny;
+        else { sy = y; plane_dir = mirror_y[a]; }
+    }
+    if (sx < 0 || sx >= g.nx) {
+        if (g.xper) sx += sx < 0 ? g.nx : -g.nx;
+        else sx = sx < 0 ? 0 : g.nx - 1;
+    }
+    return sy * g.pitch + sx;
+}
+
+// Pull the nine populations of node (x, y) from the post-collision planes `src`.
+template <int S>
+__device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__ src, int x, int y,
+                                     const Geom &g, typename Codec<S>::real f[9])
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    const int P = g.pitch;
+    const int i = y * P + x;
+    const bool interior = (x > 0) & (x < g.nx - 1) & (y > 0) & (y < g.ny - 1);
+    if (interior) {
+        f[0] = C::load(src, i, W<T>::rest);
+        f[1] = C::load(src + 1 * g.plane, i - 1, W<T>::axis);
+        f[2] = C::load(src + 2 * g.plane, i - P, W<T>::axis);
+        f[3] = C::load(src + 3 * g.plane, i + 1, W<T>::axis);
+        f[4] = C::load(src + 4 * g.plane, i + P, W<T>::axis);
+        f[5] = C::load(src + 5 * g.plane, i - P - 1, W<T>::diag);
+        f[6] = C::load(src + 6 * g.plane, i - P + 1, W<T>::diag);
+        f[7] = C::load(src + 7 * g.plane, i + P + 1, W<T>::diag);
+        f[8] = C::load(src + 8 * g.plane, i + P - 1, W<T>::diag);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 9; a++) {
+            int pa;
+            int j = edge_source(a, x, y, g, pa);
+            f[a] = C::load(src + pa * g.plane, j, weight<T>(a));
+        }
+    }
+}
+
+// Zou-He velocity inlet on the west edge: the populations entering from x < 0 (1, 5, 8) are set
+// so that sum f = rho and sum xi f = rho (ux, uy), with rho from the known populations and the
+// non-equilibrium parts bounced back.
+template <typename T>
+__device__ __forceinline__ void zou_he_west(T f[9], T ux, T uy)
+{
+    T rho = (f[0] + f[2] + f[4] + T(2) * (f[3] + f[6] + f[7])) / (T(1) - ux);
+    T half_t = T(0.5) * (f[2] - f[4]);
+    T ru6 = rho * ux * T(1.0 / 6.0);
+    f[1] = f[3] + T(2.0 / 3.0) * rho * ux;
+    f[5] = f[7] - half_t + ru6 + T(0.5) * rho * uy;
+    f[8] = f[6] + half_t + ru6 - T(0.5) * rho * uy;
+}
+
+// ---- moments and penalization ------------------------------------------------------------------
+
+template <typename T> struct Macro {
+    T rho, ux, uy;   // density and penalized velocity (Eq. 18)
+    T fx, fy;        // penalization force (Eq. 17)
+};
+
+// Eqs. 8-9 and 17-18 with dt = 1.  In a solid node (chi = 1) the velocity and force are taken in
+// the algebraically equal forms u = u_s + (j/rho - u_s) k and f = -(j - rho u_s) c with
+// k = 1/(1 + 1/(2 eta)) and c = 1/(eta + 1/2): the literal forms subtract nearly equal numbers
+// (u - u_s is ~eta) and lose about -log10(eta) digits.
+template <typename T>
+__device__ __forceinline__ Macro<T> moments(const T f[9], bool solid, T usx, T usy, T k_relax, T c_pen)
+{
+    Macro<T> m;
+    T rho = (f[0] + (f[1] + f[3])) + ((f[2] + f[4]) + ((f[5] + f[7]) + (f[6] + f[8])));
+    T jx = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));
+    T jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
+    T inv_rho = T(1) / rho;
+    m.rho = rho;
+    if (solid) {
+        m.ux = usx + (jx * inv_rho - usx) * k_relax;
+        m.uy = usy + (jy * inv_rho - usy) * k_relax;
+        m.fx = -(jx - rho * usx) * c_pen;
+        m.fy = -(jy - rho * usy) * c_pen;
+    } else {
+        m.ux = jx * inv_rho;
+        m.uy = jy * inv_rho;
+        m.fx = T(0);
+        m.fy = T(0);
+    }
+    return m;
+}
+
+// ---- collision -----------------------------------------------------------------------------------
+
+// One opposite pair (a, abar) with lattice weight w, c = xi_a . u and xf = xi_a . f.
+template <typename T>
+__device__ __forceinline__ void collide_pair(T &fa, T &fb, T c, T xf, T w, T rho, T base, T ufp,
+                                             T sp, T sm, T kp, T km)
+{
+    T feq_s = w * rho * (base + T(4.5) * c * c);      // symmetric part of Eq. 4
+    T feq_a = w * rho * (T(3) * c);                   // antisymmetric part of Eq. 4
+    T frc_s = w * (T(9) * c * xf - T(3) * ufp);       // symmetric part of Eq. 16
+    T frc_a = w * (T(3) * xf);                        // antisymmetric part of Eq. 16
+    T hs = T(0.5) * (fa + fb);
+    T ha = T(0.5) * (fa - fb);
+    T ns = hs - sp * (hs - feq_s) + kp * frc_s;
+    T na = ha - sm * (ha - feq_a) + km * frc_a;
+    fa = ns + na;
+    fb = ns - na;
+}
+
+// Two-rate collision with the split forcing term: sp/sm are the even/odd rates, kp = 1 - sp/2,
+// km = 1 - sm/2.  In place on f.
+template <typename T>
+__device__ __forceinline__ void collide(T f[9], const Macro<T> &m, T sp, T sm, T kp, T km)
+{
+    const T ux = m.ux, uy = m.uy, rho = m.rho;
+    const T base = T(1) - T(1.5) * (ux * ux + uy * uy);
+    const T ufp = ux * m.fx + uy * m.fy;
+    {
+        T feq0 = W<T>::rest * rho * base;
+        T frc0 = W<T>::rest * (T(-3) * ufp);
+        f[0] = f[0] - sp * (f[0] - feq0) + kp * frc0;
+    }
+    collide_pair(f[1], f[3], ux, m.fx, W<T>::axis, rho, base, ufp, sp, sm, kp, km);
+    collide_pair(f[2], f[4], uy, m.fy, W<T>::axis, rho, base, ufp, sp, sm, kp, km);
+    collide_pair(f[5], f[7], ux + uy, m.fx + m.fy, W<T>::diag, rho, base, ufp, sp, sm, kp, km);
+    collide_pair(f[6], f[8], uy - ux, m.fy - m.fx, W<T>::diag, rho, base, ufp, sp, sm, kp, km);
+}
+
+// Equilibrium of Eq. 4 (used to initialise).
+template <typename T>
+__device__ __forceinline__ void equilibrium(T rho, T ux, T uy, T f[9])
+{
+    const T base = T(1) - T(1.5) * (ux * ux + uy * uy);
+    const T c[9] = {T(0), ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
+#pragma unroll
+    for (int a = 0; a < 9; a++)
+        f[a] = weight<T>(a) * rho * (base + T(3) * c[a] + T(4.5) * c[a] * c[a]);
+}
+
+// ---- obstacles ------------------------------------------------------------------------------------
+
+// Per-body state at the current time, written by the body kernel: centre, translation velocity
+// and angular velocity.
+struct BodyState {
+    double cx, cy, vx, vy, omega;
+};
+
+// Rigid-body solid velocity u_s = V + omega e_z x (x - c) at node (x, y).
+template <typename T>
+__device__ __forceinline__ void solid_velocity(const BodyState &b, int x, int y, T &usx, T &usy)
+{
+    usx = T(b.vx) - T(b.omega) * (T(y) - T(b.cy));
+    usy = T(b.vy) + T(b.omega) * (T(x) - T(b.cx));
+}
+
+// ---- wave reductions ------------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Map a hardware workgroup id to a logical tile so that each XCD (workgroups are dealt to the 8
+// XCDs round-robin) works on one contiguous range of tiles, keeping x-neighbouring tiles, which
+// share cache lines through the x-shifted pulls, in the same L2.
+__device__ __forceinline__ int xcd_tile(int wg, int nwg)
+{
+    const int q = nwg >> 3, r = nwg & 7;
+    const int xcd = wg & 7, j = wg >> 3;
+    return xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
+}
+
+}  // namespace vplbm

@@ -113,21 +113,32 @@ def random_fields(nx: int, ny: int, seed: int, rho_amp=0.02, u_amp=0.03, u_mean=
 
 
 def random_bodies(nx: int, ny: int, seed: int, n: int, moving=False, rmin=2.0, rmax=None):
-    """n disks/rectangles with random centres, sizes and rigid velocities inside the lattice."""
+    """Up to n disks/rectangles with random centres and sizes inside the lattice, their boxes
+    (swept boxes when moving) at least two nodes apart.  The solid velocity is always consistent
+    with the body's own motion, so no mask forces flow through a fixed region or into another
+    body: disks spin about their centre (|omega r| <= 0.02), rectangles are at rest, and with
+    ``moving`` every body also oscillates (velocity amplitude <= 0.025)."""
     r = np.random.default_rng(seed)
     rmax = rmax if rmax is not None else max(rmin + 1.0, min(nx, ny) / 6.0)
-    out = []
+    out, boxes = [], []
     for k in range(n):
-        kind = "disk" if r.random() < 0.5 else "rect"
-        rad = min(r.uniform(rmin, rmax), min(nx, ny) / 2.0 - 2.0)
-        cx = r.uniform(rad + 1, nx - rad - 2)
-        cy = r.uniform(rad + 1, ny - rad - 2)
-        b = body(kind, cx, cy, r=rad, hx=rad * r.uniform(0.5, 1.0), hy=rad * r.uniform(0.5, 1.0),
-                 ux=r.uniform(-0.02, 0.02), uy=r.uniform(-0.02, 0.02),
-                 omega=r.uniform(-0.002, 0.002))
-        if moving:
-            b.update(ax=r.uniform(-2, 2), ay=r.uniform(-2, 2), freq=r.uniform(0.001, 0.01))
-        out.append(b)
+        for _attempt in range(200):
+            kind = "disk" if r.random() < 0.5 else "rect"
+            rad = min(r.uniform(rmin, rmax), min(nx, ny) / 2.0 - 2.0)
+            cx = r.uniform(rad + 1, nx - rad - 2)
+            cy = r.uniform(rad + 1, ny - rad - 2)
+            omega = r.uniform(-0.02, 0.02) / max(rad, 1.0) if kind == "disk" else 0.0
+            b = body(kind, cx, cy, r=rad, hx=rad * r.uniform(0.5, 1.0), hy=rad * r.uniform(0.5, 1.0),
+                     omega=omega)
+            if moving:
+                b.update(ax=r.uniform(-2, 2), ay=r.uniform(-2, 2), freq=r.uniform(0.0005, 0.002))
+            ex = (rad if kind == "disk" else b["hx"]) + abs(b["ax"]) + 1.0
+            ey = (rad if kind == "disk" else b["hy"]) + abs(b["ay"]) + 1.0
+            box = (cx - ex, cx + ex, cy - ey, cy + ey)
+            if all(box[1] < o[0] or o[1] < box[0] or box[3] < o[2] or o[3] < box[2] for o in boxes):
+                out.append(b)
+                boxes.append(box)
+                break
     return out
 
 

@@ -18,3 +18,15 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP library on a GPU; skips without a GPU, fails if the library is missing there."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU in this environment")
+    from paper_1812_05401_amd import binding
+    binding.load()
+    torch.cuda.init()
+    return binding

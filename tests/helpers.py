@@ -29,3 +29,22 @@ def rel_err(a, b):
     """max |a - b| / max |b| over all entries."""
     a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def gpu_sim(case, storage=None, device_mask=True, init=True, reduce=True, ring=0):
+    """A GPU simulation through the C ABI for a case (torch supplies the stream)."""
+    from paper_1812_05401_amd import binding as B
+    kw = {}
+    if storage is not None:
+        kw["storage"] = storage
+    import copy
+    c = copy.copy(case)
+    if storage is not None:
+        c.storage = storage
+    s = B.Simulation(c, stream="torch", reduce=reduce, ring=ring, device_mask=device_mask)
+    return s
+
+
+def force_scale(orc_obs):
+    """Scale for comparing body forces: the summed magnitude of the penalization force."""
+    return max(float(np.sum(orc_obs["fabs_sum"])), 1e-300)

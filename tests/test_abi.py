@@ -1,0 +1,96 @@
+"""The C ABI without a GPU: the library loads, exports every symbol include/vplbm.h declares, and
+rejects bad arguments on the host before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1812_05401_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "vplbm.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vplbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_calls():
+    names = declared()
+    for n in ("vplbm_create", "vplbm_set_mask", "vplbm_step", "vplbm_observables", "vplbm_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    for n in declared():
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    assert sorted(n for n, _, _ in B.SIGNATURES) == declared()
+
+
+def test_bytes_per_update():
+    assert B.vplbm_bytes_per_update("f64") == 145
+    assert B.vplbm_bytes_per_update("f32") == 73
+    assert B.vplbm_bytes_per_update("f16s") == 37
+    assert B.vplbm_bytes_per_update("bf16s") == 37
+    with pytest.raises(B.VplbmError):
+        B.vplbm_bytes_per_update(7)
+
+
+BAD = [
+    (dict(nx=2, ny=10), "sides"),
+    (dict(nx=10, ny=2), "sides"),
+    (dict(nx=10, ny=10, tau=0.5), "tau"),
+    (dict(nx=10, ny=10, tau=float("nan")), "tau"),
+    (dict(nx=10, ny=10, eta=0.0), "eta"),
+    (dict(nx=10, ny=10, collision="mrt", lam=0.0), "Lambda"),
+    (dict(nx=10, ny=10, storage=9), "storage"),
+    (dict(nx=10, ny=10, collision=5), "collision"),
+    (dict(nx=10, ny=10, rho0=-1.0), "rho0"),
+    (dict(nx=10, ny=10, bc=("periodic", "outflow", "periodic", "periodic")), "x edges"),
+    (dict(nx=10, ny=10, bc=("outflow", "velocity", "periodic", "periodic")), "x edges"),
+    (dict(nx=10, ny=10, bc=("periodic", "periodic", "freeslip", "periodic")), "y edges"),
+    (dict(nx=10, ny=10, bc=("velocity", "outflow", "freeslip", "freeslip"), u_in=(1.5, 0)), "inlet"),
+    (dict(nx=10, ny=10, ring=1), "ring"),
+    (dict(nx=100000, ny=100000), "too large"),
+]
+
+
+@pytest.mark.parametrize("kw,word", BAD)
+def test_create_rejects_bad_configs(kw, word):
+    with pytest.raises(B.VplbmError) as e:
+        B.vplbm_create(B.make_config(**kw))
+    assert e.value.code == B.EINVAL
+    assert word in str(e.value)
+
+
+def test_create_rejects_wrong_abi_version():
+    cfg = B.make_config(10, 10)
+    cfg.abi_version = 99
+    with pytest.raises(B.VplbmError) as e:
+        B.vplbm_create(cfg)
+    assert e.value.code == B.EINVAL and "abi_version" in str(e.value)
+
+
+def test_null_and_foreign_handles_are_rejected():
+    lib = B.load()
+    assert lib.vplbm_destroy(None) == B.OK
+    bogus = C.c_void_p(0xDEADBEEF)
+    obs = B.Obs()
+    n = C.c_int64()
+    s = C.c_void_p()
+    assert lib.vplbm_step(bogus, 1) == B.EINVAL
+    assert lib.vplbm_step(None, 1) == B.EINVAL
+    assert lib.vplbm_observables(bogus, C.byref(obs), None, None, None) == B.EINVAL
+    assert lib.vplbm_set_mask(bogus, None, None, 0) == B.EINVAL
+    assert lib.vplbm_destroy(bogus) == B.EINVAL
+    assert lib.vplbm_steps_done(bogus, C.byref(n)) == B.EINVAL
+    assert lib.vplbm_stream(bogus, C.byref(s)) == B.EINVAL
+    assert lib.vplbm_get_populations(bogus, None) == B.EINVAL
+    assert lib.vplbm_force_series(bogus, 0, 1, None) == B.EINVAL
+    assert "invalid handle" in B.last_error()
