@@ -156,6 +156,61 @@ int vplbm_stream(vplbm_sim s, void **stream);
    9 population stores and the 1-byte mask. */
 int vplbm_bytes_per_update(int32_t storage, int64_t *bytes);
 
+/* ---- serving pool -----------------------------------------------------------------------
+ * Many independent simulations resident on one GPU at once, advanced together: every call to
+ * vplbm_pool_advance replays one captured HIP graph of `steps_per_launch` launches of a
+ * persistent batched step kernel that walks a device table of tiles spanning all resident
+ * simulations (each simulation's per-node arithmetic is the single-simulation step's), then
+ * retires the finished ones and admits queued requests, first come first served, while the
+ * memory budget and the slots allow.  A simulation's results do not depend on what else is
+ * resident: fields are bitwise identical alone and in a mix, and the final mass and body forces
+ * are summed per tile in a fixed order.  Bodies must be static (no prescribed motion) and are
+ * rasterized on the device.
+ */
+typedef struct vplbm_pool_s *vplbm_pool;
+
+enum vplbm_request_state {
+    VPLBM_QUEUED = 0,    /* submitted, waiting for memory or a slot */
+    VPLBM_RUNNING = 1,   /* resident, advancing */
+    VPLBM_DONE = 2,      /* finished; results held until vplbm_pool_result */
+    VPLBM_FAILED = 3     /* became unstable; results hold the last observables */
+};
+
+typedef struct {
+    uint32_t abi_version;       /* must be VPLBM_ABI_VERSION */
+    uint64_t budget_bytes;      /* device memory the resident simulations may use together */
+    int32_t max_slots;          /* resident simulations at most, 1..1024 */
+    int32_t steps_per_launch;   /* steps per vplbm_pool_advance (graph length), 1..4096 */
+    void *stream;               /* hipStream_t for all pool work; NULL: a stream of the pool's */
+} vplbm_pool_config;
+
+int vplbm_pool_create(const vplbm_pool_config *cfg, vplbm_pool *out);
+
+/* Queue a simulation for `nsteps` >= 1 steps from its uniform initial state (cfg->stream is
+   ignored; cfg->reduce is ignored: the final step's mass and forces are always reduced).
+   keep_fields = 1 also keeps the final density and velocity fields for vplbm_pool_result.
+   Returns VPLBM_EBUDGET if the simulation alone exceeds the budget, VPLBM_EINVAL for a bad
+   config or moving bodies.  *id receives the request id (>= 0). */
+int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *bodies,
+                      int32_t nbodies, int64_t nsteps, int32_t keep_fields, int64_t *id);
+
+/* Wait for the previous launch, retire finished simulations, admit queued ones, and launch the
+   next chunk of steps (asynchronous).  Any output pointer may be NULL. */
+int vplbm_pool_advance(vplbm_pool p, int32_t *running, int32_t *queued, int32_t *finished_total);
+
+/* State and steps done of a request. */
+int vplbm_pool_status(vplbm_pool p, int64_t id, int32_t *state, int64_t *steps_done);
+
+/* Results of a DONE or FAILED request: final observables and, if the request kept them, the
+   host FP64 fields (nx*ny each; pass NULL to skip).  Releases the request. */
+int vplbm_pool_result(vplbm_pool p, int64_t id, vplbm_obs *out, double *rho, double *ux, double *uy);
+
+/* Device bytes the pool charges a simulation against its budget. */
+int vplbm_pool_bytes_needed(const vplbm_config *cfg, uint64_t *bytes);
+
+/* Wait for outstanding work, free everything.  NULL-safe. */
+int vplbm_pool_destroy(vplbm_pool p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,6 +52,11 @@ class Body(C.Structure):
                 ("freq", C.c_double)]
 
 
+class PoolConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("budget_bytes", C.c_uint64), ("max_slots", C.c_int32),
+                ("steps_per_launch", C.c_int32), ("stream", C.c_void_p)]
+
+
 class Obs(C.Structure):
     _fields_ = [("step", C.c_int64), ("mass", C.c_double), ("fx", C.c_double * MAX_BODIES),
                 ("fy", C.c_double * MAX_BODIES), ("nbodies", C.c_int32), ("status", C.c_int32)]
@@ -74,7 +79,17 @@ SIGNATURES = [
     ("vplbm_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("vplbm_stream", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     ("vplbm_bytes_per_update", C.c_int, [C.c_int32, C.POINTER(C.c_int64)]),
+    ("vplbm_pool_create", C.c_int, [C.POINTER(PoolConfig), C.POINTER(C.c_void_p)]),
+    ("vplbm_pool_submit", C.c_int, [C.c_void_p, C.POINTER(Config), C.POINTER(Body), C.c_int32,
+                                     C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
+    ("vplbm_pool_advance", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]),
+    ("vplbm_pool_status", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    ("vplbm_pool_result", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Obs), _dp, _dp, _dp]),
+    ("vplbm_pool_bytes_needed", C.c_int, [C.POINTER(Config), C.POINTER(C.c_uint64)]),
+    ("vplbm_pool_destroy", C.c_int, [C.c_void_p]),
 ]
+QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
 
 _lib = None
 
@@ -310,3 +325,79 @@ class Simulation:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---- serving pool -----------------------------------------------------------------------------
+
+def _obs_dict(o):
+    nb = o.nbodies
+    return {"step": o.step, "mass": o.mass, "fx": np.array(o.fx[:nb]), "fy": np.array(o.fy[:nb]),
+            "status": o.status}
+
+
+def case_config(case, **kw):
+    return make_config(case.nx, case.ny, collision=case.collision, storage=case.storage,
+                       tau=case.tau, lam=case.lam, eta=case.eta, rho0=case.rho0, u0=case.u0,
+                       bc=case.bc, u_in=case.u_in, **kw)
+
+
+def vplbm_pool_bytes_needed(case):
+    b = C.c_uint64()
+    check(load().vplbm_pool_bytes_needed(C.byref(case_config(case)), C.byref(b)))
+    return b.value
+
+
+class Pool:
+    """Continuous-batching pool: ``submit`` queues simulations, ``advance`` retires finished
+    ones, admits queued ones within the memory budget and launches the next chunk of steps for
+    every resident simulation."""
+
+    def __init__(self, budget_bytes, max_slots=64, steps_per_launch=64, stream=None):
+        cfg = PoolConfig(ABI_VERSION, int(budget_bytes), int(max_slots), int(steps_per_launch),
+                         stream)
+        h = C.c_void_p()
+        check(load().vplbm_pool_create(C.byref(cfg), C.byref(h)))
+        self.h = h.value
+        self.shapes = {}
+
+    def submit(self, case, nsteps=None, keep_fields=False):
+        bodies = case.bodies
+        arr = (Body * max(1, len(bodies)))(*[make_body(b) for b in bodies])
+        rid = C.c_int64()
+        check(load().vplbm_pool_submit(self.h, C.byref(case_config(case)), arr, len(bodies),
+                                       int(nsteps if nsteps is not None else case.steps),
+                                       1 if keep_fields else 0, C.byref(rid)))
+        self.shapes[rid.value] = (case.ny, case.nx)
+        return rid.value
+
+    def advance(self):
+        r, q, f = C.c_int32(), C.c_int32(), C.c_int32()
+        check(load().vplbm_pool_advance(self.h, C.byref(r), C.byref(q), C.byref(f)))
+        return r.value, q.value, f.value
+
+    def status(self, rid):
+        st, n = C.c_int32(), C.c_int64()
+        check(load().vplbm_pool_status(self.h, int(rid), C.byref(st), C.byref(n)))
+        return st.value, n.value
+
+    def result(self, rid, fields=False):
+        o = Obs()
+        ptrs = [None, None, None]
+        out = None
+        if fields:
+            out = tuple(np.empty(self.shapes[rid]) for _ in range(3))
+            ptrs = [_ptr(a) for a in out]
+        check(load().vplbm_pool_result(self.h, int(rid), C.byref(o), *ptrs))
+        self.shapes.pop(rid, None)
+        return (_obs_dict(o), out) if fields else _obs_dict(o)
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(load().vplbm_pool_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

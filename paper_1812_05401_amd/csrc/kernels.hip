@@ -71,18 +71,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if (active) {
-            T f[9];
-            pull<S>(src, x, y, a.g, f);
-            if (a.g.inlet && x == 0) zou_he_west(f, T(a.uin_x), T(a.uin_y));
-            const int i = y * a.g.pitch + x;
-            id = a.mask[i];
-            T usx = T(0), usy = T(0);
-            if (id) solid_velocity(a.bodies[id - 1], x, y, usx, usy);
-            const Macro<T> m = moments(f, id != 0, usx, usy, T(a.k_relax), T(a.c_pen));
-            collide(f, m, T(a.sp), T(a.sm), T(a.kp), T(a.km));
-            C::store(dst, i, f[0], W<T>::rest);
-#pragma unroll
-            for (int k = 1; k < 9; k++) C::store(dst + k * a.g.plane, i, f[k], weight<T>(k));
+            const Macro<T> m = update_node<S>(src, dst, a.mask, a.bodies, a.g, a.p, x, y, id);
             const double rho_d = double(m.rho);
             mass += rho_d;
             fx_d = double(m.fx);
@@ -170,11 +159,11 @@ __global__ __launch_bounds__(kBlock) void readback_kernel(StepArgs a, double *rh
     const int x = node % a.g.nx, y = node / a.g.nx;
     T f[9];
     pull<S>(static_cast<const E *>(a.src), x, y, a.g, f);
-    if (a.g.inlet && x == 0) zou_he_west(f, T(a.uin_x), T(a.uin_y));
+    if (a.g.inlet && x == 0) zou_he_west(f, T(a.p.uin_x), T(a.p.uin_y));
     const int id = a.mask[y * a.g.pitch + x];
     T usx = T(0), usy = T(0);
     if (id) solid_velocity(a.bodies[id - 1], x, y, usx, usy);
-    const Macro<T> m = moments(f, id != 0, usx, usy, T(a.k_relax), T(a.c_pen));
+    const Macro<T> m = moments(f, id != 0, usx, usy, T(a.p.k_relax), T(a.p.c_pen));
     rho[node] = double(m.rho);
     ux[node] = double(m.ux);
     uy[node] = double(m.uy);

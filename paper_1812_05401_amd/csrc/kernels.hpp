@@ -39,9 +39,7 @@ struct StepArgs {
     int ntx;                 // tiles along x
     int bx_log2, by;         // workgroup = (1 << bx_log2) x by threads
     int rows;                // each thread updates `rows` nodes, by rows apart
-    double sp, sm, kp, km;   // even/odd relaxation rates and 1 - s/2
-    double k_relax, c_pen;   // 1/(1 + 1/(2 eta)) and 1/(eta + 1/2)
-    double uin_x, uin_y;
+    NodeParams p;
 };
 
 struct TileShape {

@@ -240,6 +240,41 @@ __device__ __forceinline__ void solid_velocity(const BodyState &b, int x, int y,
     usy = T(b.vy) + T(b.omega) * (T(x) - T(b.cx));
 }
 
+// ---- one lattice update ------------------------------------------------------------------------
+
+// Relaxation, penalization and inlet parameters of one simulation (FP64; each kernel converts
+// them to its compute type the same way).
+struct NodeParams {
+    double sp, sm, kp, km;   // even/odd relaxation rates and 1 - s/2
+    double k_relax, c_pen;   // 1/(1 + 1/(2 eta)) and 1/(eta + 1/2)
+    double uin_x, uin_y;     // inlet velocity
+};
+
+// The whole step at node (x, y): pull, edges, moments and penalization, collision, store.
+// Returns the moments (density, penalization force) for the reductions and the body id.
+template <int S>
+__device__ __forceinline__ Macro<typename Codec<S>::real>
+update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::elem *__restrict__ dst,
+            const uint8_t *__restrict__ mask, const BodyState *__restrict__ bodies, const Geom &g,
+            const NodeParams &p, int x, int y, int &id)
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    T f[9];
+    pull<S>(src, x, y, g, f);
+    if (g.inlet && x == 0) zou_he_west(f, T(p.uin_x), T(p.uin_y));
+    const int i = y * g.pitch + x;
+    id = mask[i];
+    T usx = T(0), usy = T(0);
+    if (id) solid_velocity(bodies[id - 1], x, y, usx, usy);
+    const Macro<T> m = moments(f, id != 0, usx, usy, T(p.k_relax), T(p.c_pen));
+    collide(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));
+    C::store(dst, i, f[0], W<T>::rest);
+#pragma unroll
+    for (int k = 1; k < 9; k++) C::store(dst + k * g.plane, i, f[k], weight<T>(k));
+    return m;
+}
+
 // ---- wave reductions ------------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double v)

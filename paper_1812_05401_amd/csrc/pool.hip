@@ -1,0 +1,608 @@
+// Serving pool: many resident VP-LBM simulations advanced together by one persistent batched
+// kernel replayed from a captured HIP graph (see the pool section of include/vplbm.h).
+//
+// Device side.  A descriptor per slot (buffers, geometry, parameters, steps done / target) and a
+// table of 64 x 4 tiles covering every resident simulation.  The batched kernel walks the tile
+// table grid-stride; each tile runs the same per-node update as the single-simulation step, so a
+// simulation's fields do not depend on its co-residents.  On a simulation's final step each tile
+// writes its FP64 partial sums (mass, body forces) to its own slot, with a fixed summation order
+// inside the tile; the tick kernel that follows every step folds them in tile order (so the
+// final observables are bitwise independent of the mix) and advances the step counters.
+//
+// Host side.  Between graph replays: retire finished simulations (copy results, free memory),
+// admit queued requests first come first served while the memory budget and slots allow, rebuild
+// the tile table.  The graph itself never changes: it reads the tables from device memory.
+#include <math.h>
+#include <string.h>
+
+#include <deque>
+#include <map>
+#include <mutex>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace vplbm;
+
+namespace vplbm {
+
+constexpr int kPoolTileW = 64, kPoolTileH = 4;   // one node per thread, 256 threads
+constexpr int kPoolMaxSlots = 1024;
+
+struct PoolSim {
+    void *buf[2];
+    const uint8_t *mask;
+    const BodyState *bodies;
+    double *partials;        // [ntiles][kRingWidth] of the final step
+    Geom g;
+    NodeParams p;
+    int storage;
+    int ntx, ntiles;
+    int active;
+    long long done, target;
+    unsigned status;
+    double obs[kRingWidth];  // folded final observables
+};
+
+struct TileRef {
+    int slot, tile;
+};
+
+template <int S>
+__device__ __forceinline__ double pool_node(const PoolSim &d, int parity, int x, int y, double &fx,
+                                            double &fy, int &id)
+{
+    using C = Codec<S>;
+    using E = typename C::elem;
+    const E *src = static_cast<const E *>(d.buf[parity]);
+    E *dst = static_cast<E *>(d.buf[parity ^ 1]);
+    const auto m = update_node<S>(src, dst, d.mask, d.bodies, d.g, d.p, x, y, id);
+    fx = double(m.fx);
+    fy = double(m.fy);
+    return double(m.rho);
+}
+
+__global__ __launch_bounds__(kBlock) void pool_step_kernel(PoolSim *sims, const TileRef *tiles,
+                                                           const int *ntiles)
+{
+    __shared__ double part[kBlock / 64][kRingWidth];
+    const int n = *ntiles;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = xcd_tile(blockIdx.x, gridDim.x); k < n; k += gridDim.x) {
+        const TileRef tr = tiles[k];
+        const PoolSim &d = sims[tr.slot];
+        const long long done = d.done;
+        if (!d.active || done >= d.target) continue;          // uniform over the workgroup
+        const int x = (tr.tile % d.ntx) * kPoolTileW + lane;
+        const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
+        const bool active = (x < d.g.nx) & (y < d.g.ny);
+        const int parity = (int)(done & 1);
+        double rho = 0.0, fx = 0.0, fy = 0.0;
+        int id = 0;
+        if (active) {
+            switch (d.storage) {
+            case kF64: rho = pool_node<kF64>(d, parity, x, y, fx, fy, id); break;
+            case kF32: rho = pool_node<kF32>(d, parity, x, y, fx, fy, id); break;
+            case kF16S: rho = pool_node<kF16S>(d, parity, x, y, fx, fy, id); break;
+            default: rho = pool_node<kBF16S>(d, parity, x, y, fx, fy, id); break;
+            }
+        }
+        const bool bad = active && !(rho > 0.0 && rho < 1e30);
+        if (__ballot(bad) && lane == 0) atomicOr(&sims[tr.slot].status, 1u);
+        if (done + 1 == d.target) {
+            // Final step: deterministic per-tile sums (wave shuffles, then the four waves in order).
+            if (lane < kRingWidth) part[wave][lane] = 0.0;
+            const double mw = wave_sum(rho);
+            if (lane == 0) part[wave][0] = mw;
+            unsigned long long solid = __ballot(id != 0);
+            while (solid) {
+                const int lead = __ffsll((unsigned long long)solid) - 1;
+                const int b = __shfl(id, lead, 64);
+                const bool mine = id == b;
+                const double sx = wave_sum(mine ? -fx : 0.0);
+                const double sy = wave_sum(mine ? -fy : 0.0);
+                if (lane == 0) {
+                    part[wave][1 + 2 * (b - 1)] = sx;
+                    part[wave][2 + 2 * (b - 1)] = sy;
+                }
+                solid &= ~__ballot(mine);
+            }
+            __syncthreads();
+            if (threadIdx.x < kRingWidth) {
+                double v = 0.0;
+                for (int w = 0; w < kBlock / 64; w++) v += part[w][threadIdx.x];
+                d.partials[(size_t)tr.tile * kRingWidth + threadIdx.x] = v;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// After every batched step: fold the final step's partials (tile order) and count the step.
+__global__ void pool_tick_kernel(PoolSim *sims)
+{
+    PoolSim &d = sims[blockIdx.x];
+    if (!d.active) return;
+    const long long done = d.done;
+    if (done >= d.target) return;
+    if (done + 1 == d.target && threadIdx.x < kRingWidth) {
+        double v = 0.0;
+        for (int t = 0; t < d.ntiles; t++) v += d.partials[(size_t)t * kRingWidth + threadIdx.x];
+        d.obs[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) d.done = done + 1;
+}
+
+}  // namespace vplbm
+
+namespace {
+
+struct Request {
+    int64_t id = -1;
+    vplbm_config cfg{};
+    std::vector<vplbm_body> bodies;
+    int64_t nsteps = 0;
+    int keep_fields = 0;
+    int state = VPLBM_QUEUED;
+    int slot = -1;
+    uint64_t bytes = 0;
+    int64_t done = 0;
+    vplbm_obs obs{};
+    std::vector<double> rho, ux, uy;
+    // device memory while resident
+    void *buf[2] = {nullptr, nullptr};
+    uint8_t *mask = nullptr;
+    BodyParams *params = nullptr;
+    BodyState *state_dev = nullptr;
+    double *partials = nullptr;
+};
+
+int pool_geometry(const vplbm_config &c, Geom &g, int &ntx, int &ntiles)
+{
+    g.nx = c.nx;
+    g.ny = c.ny;
+    g.pitch = (c.nx + 63) / 64 * 64;
+    g.plane = g.pitch * c.ny;
+    g.xper = c.bc_xlo == VPLBM_PERIODIC;
+    g.yper = c.bc_ylo == VPLBM_PERIODIC;
+    g.inlet = c.bc_xlo == VPLBM_VELOCITY;
+    ntx = (c.nx + kPoolTileW - 1) / kPoolTileW;
+    ntiles = ntx * ((c.ny + kPoolTileH - 1) / kPoolTileH);
+    return VPLBM_OK;
+}
+
+uint64_t bytes_needed(const vplbm_config &c)
+{
+    Geom g;
+    int ntx, ntiles;
+    pool_geometry(c, g, ntx, ntiles);
+    const uint64_t pop = (uint64_t)9 * g.plane * elem_bytes(c.storage);
+    return 2 * pop + (uint64_t)g.pitch * g.ny + sizeof(BodyParams) * kMaxBodies +
+           sizeof(BodyState) * kMaxBodies + (uint64_t)ntiles * kRingWidth * sizeof(double);
+}
+
+std::mutex g_pool_mu;
+std::unordered_set<const void *> g_pools;
+
+}  // namespace
+
+struct vplbm_pool_s {
+    vplbm_pool_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph = nullptr;
+    PoolSim *d_sims = nullptr;
+    TileRef *d_tiles = nullptr;
+    int *d_ntiles = nullptr;
+    long long *d_zero = nullptr;
+    double *staging = nullptr;
+    size_t staging_bytes = 0;
+    int tile_cap = 0;
+    int grid = 2048;
+    std::vector<PoolSim> h_sims;
+    std::vector<int64_t> slot_req;        // request id per slot (-1 free)
+    std::map<int64_t, Request> reqs;
+    std::deque<int64_t> queue;
+    int64_t next_id = 0;
+    uint64_t used = 0;
+    bool in_flight = false;
+    int32_t finished = 0;
+};
+
+namespace {
+
+bool pool_valid(const void *p)
+{
+    if (!p) return false;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    return g_pools.count(p) != 0;
+}
+
+void free_request_memory(vplbm_pool p, Request &r)
+{
+    void *ptrs[] = {r.buf[0], r.buf[1], r.mask, r.params, r.state_dev, r.partials};
+    for (void *q : ptrs)
+        if (q) (void)hipFreeAsync(q, p->stream);
+    r.buf[0] = r.buf[1] = nullptr;
+    r.mask = nullptr;
+    r.params = nullptr;
+    r.state_dev = nullptr;
+    r.partials = nullptr;
+}
+
+int ensure_pool_staging(vplbm_pool p, size_t bytes)
+{
+    if (p->staging_bytes >= bytes) return VPLBM_OK;
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if (p->staging) HIP_TRY(hipFree(p->staging));
+    p->staging = nullptr;
+    p->staging_bytes = 0;
+    if (hipMalloc(&p->staging, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(VPLBM_ENOMEM, "cannot allocate %zu bytes of staging memory", bytes);
+    }
+    p->staging_bytes = bytes;
+    return VPLBM_OK;
+}
+
+StepArgs args_for(const PoolSim &d, const Request &r, long long *t_zero)
+{
+    StepArgs a{};
+    const int parity = (int)(d.done & 1);
+    a.src = d.buf[parity];
+    a.dst = d.buf[parity];
+    a.mask = d.mask;
+    a.bodies = d.bodies;
+    a.t_base = t_zero;
+    a.g = d.g;
+    a.p = d.p;
+    (void)r;
+    return a;
+}
+
+// Copy a finished simulation's results to the host and release its slot and memory.
+int retire(vplbm_pool p, int slot)
+{
+    Request &r = p->reqs[p->slot_req[slot]];
+    const PoolSim &d = p->h_sims[slot];
+    r.done = d.done;
+    r.obs.step = d.done - 1;
+    r.obs.mass = d.obs[0];
+    for (int k = 0; k < kMaxBodies; k++) {
+        r.obs.fx[k] = d.obs[1 + 2 * k];
+        r.obs.fy[k] = d.obs[2 + 2 * k];
+    }
+    r.obs.nbodies = (int32_t)r.bodies.size();
+    r.obs.status = (d.status & 1u) ? 1 : 0;
+    r.state = r.obs.status ? VPLBM_FAILED : VPLBM_DONE;
+    if (r.keep_fields) {
+        const size_t n = (size_t)d.g.nx * d.g.ny;
+        int rc = ensure_pool_staging(p, 3 * n * sizeof(double));
+        if (rc) return rc;
+        r.rho.resize(n);
+        r.ux.resize(n);
+        r.uy.resize(n);
+        HIP_TRY(launch_readback(d.storage, args_for(d, r, p->d_zero), p->staging, p->staging + n, p->staging + 2 * n, p->stream));
+        HIP_TRY(hipMemcpyAsync(r.rho.data(), p->staging, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipMemcpyAsync(r.ux.data(), p->staging + n, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipMemcpyAsync(r.uy.data(), p->staging + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipStreamSynchronize(p->stream));
+    }
+    free_request_memory(p, r);
+    p->used -= r.bytes;
+    r.slot = -1;
+    p->slot_req[slot] = -1;
+    memset(&p->h_sims[slot], 0, sizeof(PoolSim));
+    p->finished++;
+    return VPLBM_OK;
+}
+
+// Allocate and initialise a queued request in a free slot.  Returns 1 if admitted, 0 if it does
+// not fit now, < 0 on error.
+int admit(vplbm_pool p, Request &r, int slot)
+{
+    if (p->used + r.bytes > p->cfg.budget_bytes) return 0;
+    PoolSim d{};
+    pool_geometry(r.cfg, d.g, d.ntx, d.ntiles);
+    const size_t pop = (size_t)9 * d.g.plane * elem_bytes(r.cfg.storage);
+    struct { void **ptr; size_t n; } allocs[] = {
+        {&r.buf[0], pop}, {&r.buf[1], pop}, {(void **)&r.mask, (size_t)d.g.pitch * d.g.ny},
+        {(void **)&r.params, sizeof(BodyParams) * kMaxBodies},
+        {(void **)&r.state_dev, sizeof(BodyState) * kMaxBodies},
+        {(void **)&r.partials, (size_t)d.ntiles * kRingWidth * sizeof(double)},
+    };
+    for (auto &a : allocs) {
+        if (hipMallocAsync(a.ptr, a.n, p->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            free_request_memory(p, r);
+            return 0;   // the device is fuller than the budget says; retry after retirements
+        }
+    }
+    BodyParams hp[kMaxBodies];
+    memset(hp, 0, sizeof hp);
+    const int nb = (int)r.bodies.size();
+    for (int k = 0; k < nb; k++) {
+        const vplbm_body &b = r.bodies[k];
+        hp[k].kind = b.kind; hp[k].cx = b.cx; hp[k].cy = b.cy; hp[k].r = b.r; hp[k].hx = b.hx;
+        hp[k].hy = b.hy; hp[k].ux = b.ux; hp[k].uy = b.uy; hp[k].omega = b.omega;
+    }
+    HIP_TRY(hipMemcpyAsync(r.params, hp, sizeof hp, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(launch_bodies(r.params, r.state_dev, nb, p->d_zero, 0, p->stream));
+    HIP_TRY(launch_mask(r.mask, d.g, r.params, r.state_dev, nb, 0, 0, d.g.nx, d.g.ny, p->stream));
+    d.buf[0] = r.buf[0];
+    d.buf[1] = r.buf[1];
+    d.mask = r.mask;
+    d.bodies = r.state_dev;
+    d.partials = r.partials;
+    d.p = node_params(r.cfg);
+    d.storage = r.cfg.storage;
+    d.active = 1;
+    d.done = 0;
+    d.target = r.nsteps;
+    StepArgs a{};
+    a.dst = d.buf[0];
+    a.mask = d.mask;
+    a.bodies = d.bodies;
+    a.g = d.g;
+    a.p = d.p;
+    HIP_TRY(launch_init(d.storage, a, nullptr, nullptr, nullptr, r.cfg.rho0, r.cfg.ux0, r.cfg.uy0, p->stream));
+    p->h_sims[slot] = d;
+    r.slot = slot;
+    r.state = VPLBM_RUNNING;
+    p->used += r.bytes;
+    return 1;
+}
+
+int ensure_pool_graph(vplbm_pool p)
+{
+    if (p->graph) return VPLBM_OK;
+    if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < p->cfg.steps_per_launch && e == hipSuccess; j++) {
+        pool_step_kernel<<<dim3(p->grid), dim3(kBlock), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+            pool_tick_kernel<<<dim3(p->cfg.max_slots), dim3(64), 0, p->cap_stream>>>(p->d_sims);
+            e = hipGetLastError();
+        }
+    }
+    hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(VPLBM_EHIP, "pool graph capture failed: %s", hipGetErrorString(e));
+    }
+    HIP_TRY(e2);
+    e = hipGraphInstantiate(&p->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(e);
+    return VPLBM_OK;
+}
+
+int upload_tables(vplbm_pool p)
+{
+    std::vector<TileRef> tiles;
+    for (int s = 0; s < p->cfg.max_slots; s++) {
+        const PoolSim &d = p->h_sims[s];
+        if (!d.active) continue;
+        for (int t = 0; t < d.ntiles; t++) tiles.push_back({s, t});
+    }
+    if ((int)tiles.size() > p->tile_cap) {
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        if (p->d_tiles) HIP_TRY(hipFree(p->d_tiles));
+        p->d_tiles = nullptr;
+        int cap = p->tile_cap ? p->tile_cap : 4096;
+        while (cap < (int)tiles.size()) cap *= 2;
+        if (hipMalloc(&p->d_tiles, sizeof(TileRef) * cap) != hipSuccess) {
+            (void)hipGetLastError();
+            p->tile_cap = 0;
+            return fail(VPLBM_ENOMEM, "cannot allocate the tile table");
+        }
+        p->tile_cap = cap;
+        if (p->graph) {   // the graph holds the table pointer: capture again
+            HIP_TRY(hipGraphExecDestroy(p->graph));
+            p->graph = nullptr;
+        }
+    }
+    const int n = (int)tiles.size();
+    if (n) HIP_TRY(hipMemcpyAsync(p->d_tiles, tiles.data(), sizeof(TileRef) * n, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_ntiles, &n, sizeof n, hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_sims, p->h_sims.data(), sizeof(PoolSim) * p->cfg.max_slots, hipMemcpyHostToDevice, p->stream));
+    // The host copies above read pageable memory that changes on the next call: finish them.
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    return VPLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vplbm_pool_bytes_needed(const vplbm_config *cfg, uint64_t *bytes)
+{
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    if (!bytes) return fail(VPLBM_EINVAL, "bytes is NULL");
+    *bytes = bytes_needed(*cfg);
+    return VPLBM_OK;
+}
+
+int vplbm_pool_create(const vplbm_pool_config *cfg, vplbm_pool *out)
+{
+    if (!out) return fail(VPLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(VPLBM_EINVAL, "config is NULL");
+    if (cfg->abi_version != VPLBM_ABI_VERSION) return fail(VPLBM_EINVAL, "abi_version %u, library is %d", cfg->abi_version, VPLBM_ABI_VERSION);
+    if (cfg->max_slots < 1 || cfg->max_slots > kPoolMaxSlots) return fail(VPLBM_EINVAL, "max_slots must be in [1, %d]", kPoolMaxSlots);
+    if (cfg->steps_per_launch < 1 || cfg->steps_per_launch > 4096) return fail(VPLBM_EINVAL, "steps_per_launch must be in [1, 4096]");
+    if (cfg->budget_bytes == 0) return fail(VPLBM_EINVAL, "budget_bytes must be > 0");
+    vplbm_pool p = new vplbm_pool_s();
+    p->cfg = *cfg;
+    if (cfg->stream) {
+        p->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete p;
+            return fail(VPLBM_EHIP, "cannot create a stream");
+        }
+        p->own_stream = true;
+    }
+    p->h_sims.assign(cfg->max_slots, PoolSim{});
+    memset(p->h_sims.data(), 0, sizeof(PoolSim) * cfg->max_slots);
+    p->slot_req.assign(cfg->max_slots, -1);
+    hipError_t e = hipMalloc(&p->d_sims, sizeof(PoolSim) * cfg->max_slots);
+    if (e == hipSuccess) e = hipMalloc(&p->d_ntiles, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_zero, sizeof(long long));
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_zero, 0, sizeof(long long), p->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_ntiles, 0, sizeof(int), p->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_sims, 0, sizeof(PoolSim) * cfg->max_slots, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (p->d_sims) (void)hipFree(p->d_sims);
+        if (p->d_ntiles) (void)hipFree(p->d_ntiles);
+        if (p->d_zero) (void)hipFree(p->d_zero);
+        if (p->own_stream) (void)hipStreamDestroy(p->stream);
+        delete p;
+        return fail(VPLBM_ENOMEM, "cannot allocate the pool tables: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        g_pools.insert(p);
+    }
+    *out = p;
+    return VPLBM_OK;
+}
+
+int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *bodies,
+                      int32_t nbodies, int64_t nsteps, int32_t keep_fields, int64_t *id)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    if (!id) return fail(VPLBM_EINVAL, "id is NULL");
+    int rc = check_config(cfg);
+    if (rc) return rc;
+    rc = check_bodies(bodies, nbodies);
+    if (rc) return rc;
+    for (int k = 0; k < nbodies; k++)
+        if (bodies[k].freq != 0.0 && (bodies[k].ax != 0.0 || bodies[k].ay != 0.0))
+            return fail(VPLBM_EINVAL, "pool simulations take static bodies only (body %d moves)", k);
+    if (nsteps < 1) return fail(VPLBM_EINVAL, "nsteps must be >= 1");
+    const uint64_t need = bytes_needed(*cfg);
+    if (need > p->cfg.budget_bytes)
+        return fail(VPLBM_EBUDGET, "simulation needs %llu bytes, pool budget is %llu", (unsigned long long)need, (unsigned long long)p->cfg.budget_bytes);
+    Request r;
+    r.id = p->next_id++;
+    r.cfg = *cfg;
+    r.bodies.assign(bodies, bodies + nbodies);
+    r.nsteps = nsteps;
+    r.keep_fields = keep_fields ? 1 : 0;
+    r.bytes = need;
+    p->reqs[r.id] = r;
+    p->queue.push_back(r.id);
+    *id = r.id;
+    return VPLBM_OK;
+}
+
+int vplbm_pool_advance(vplbm_pool p, int32_t *running, int32_t *queued, int32_t *finished_total)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    if (p->in_flight) {
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        p->in_flight = false;
+        HIP_TRY(hipMemcpy(p->h_sims.data(), p->d_sims, sizeof(PoolSim) * p->cfg.max_slots, hipMemcpyDeviceToHost));
+    }
+    bool changed = false;
+    for (int s = 0; s < p->cfg.max_slots; s++) {
+        PoolSim &d = p->h_sims[s];
+        if (!d.active) continue;
+        p->reqs[p->slot_req[s]].done = d.done;
+        if (d.done >= d.target || (d.status & 1u)) {
+            int rc = retire(p, s);
+            if (rc) return rc;
+            changed = true;
+        }
+    }
+    // First come, first served: the head of the queue waits for room rather than being passed.
+    while (!p->queue.empty()) {
+        int slot = -1;
+        for (int s = 0; s < p->cfg.max_slots; s++)
+            if (p->slot_req[s] < 0) { slot = s; break; }
+        if (slot < 0) break;
+        Request &r = p->reqs[p->queue.front()];
+        int rc = admit(p, r, slot);
+        if (rc < 0) return rc;
+        if (rc == 0) break;
+        p->slot_req[slot] = r.id;
+        p->queue.pop_front();
+        changed = true;
+    }
+    int nrun = 0;
+    for (int s = 0; s < p->cfg.max_slots; s++) nrun += p->h_sims[s].active ? 1 : 0;
+    if (changed) {
+        int rc = upload_tables(p);
+        if (rc) return rc;
+    }
+    if (nrun > 0) {
+        int rc = ensure_pool_graph(p);
+        if (rc) return rc;
+        HIP_TRY(hipGraphLaunch(p->graph, p->stream));
+        p->in_flight = true;
+    }
+    if (running) *running = nrun;
+    if (queued) *queued = (int32_t)p->queue.size();
+    if (finished_total) *finished_total = p->finished;
+    return VPLBM_OK;
+}
+
+int vplbm_pool_status(vplbm_pool p, int64_t id, int32_t *state, int64_t *steps_done)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    auto it = p->reqs.find(id);
+    if (it == p->reqs.end()) return fail(VPLBM_EINVAL, "unknown request %lld", (long long)id);
+    if (state) *state = it->second.state;
+    if (steps_done) *steps_done = it->second.done;
+    return VPLBM_OK;
+}
+
+int vplbm_pool_result(vplbm_pool p, int64_t id, vplbm_obs *out, double *rho, double *ux, double *uy)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    auto it = p->reqs.find(id);
+    if (it == p->reqs.end()) return fail(VPLBM_EINVAL, "unknown request %lld", (long long)id);
+    Request &r = it->second;
+    if (r.state != VPLBM_DONE && r.state != VPLBM_FAILED) return fail(VPLBM_ESTATE, "request %lld has not finished", (long long)id);
+    if ((rho || ux || uy) && !r.keep_fields) return fail(VPLBM_EINVAL, "request %lld did not keep its fields", (long long)id);
+    if (out) *out = r.obs;
+    const size_t n = r.rho.size();
+    if (rho) memcpy(rho, r.rho.data(), n * sizeof(double));
+    if (ux) memcpy(ux, r.ux.data(), n * sizeof(double));
+    if (uy) memcpy(uy, r.uy.data(), n * sizeof(double));
+    p->reqs.erase(it);
+    return VPLBM_OK;
+}
+
+int vplbm_pool_destroy(vplbm_pool p)
+{
+    if (!p) return VPLBM_OK;
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    (void)hipStreamSynchronize(p->stream);
+    for (auto &kv : p->reqs) free_request_memory(p, kv.second);
+    (void)hipStreamSynchronize(p->stream);
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    void *ptrs[] = {p->d_sims, p->d_tiles, p->d_ntiles, p->d_zero, p->staging};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->own_stream) (void)hipStreamDestroy(p->stream);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        g_pools.erase(p);
+    }
+    delete p;
+    return VPLBM_OK;
+}
+
+}  // extern "C"

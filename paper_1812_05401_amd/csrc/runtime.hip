@@ -15,14 +15,17 @@
 #include <string>
 #include <unordered_set>
 
+#include "internal.hpp"
 #include "kernels.hpp"
 #include "vplbm.h"
 
 using namespace vplbm;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace vplbm {
 
 int fail(int code, const char *fmt, ...)
 {
@@ -35,11 +38,7 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                             \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(VPLBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+
 
 int elem_bytes(int storage)
 {
@@ -51,6 +50,10 @@ int elem_bytes(int storage)
     default: return 0;
     }
 }
+
+}  // namespace vplbm
+
+namespace {
 
 int graph_chunk()
 {
@@ -92,7 +95,7 @@ struct vplbm_sim_s {
     int graph_k = 0;
     int64_t steps = 0;
     bool unstable = false;
-    double sp = 0, sm = 0, kp = 0, km = 0, k_relax = 0, c_pen = 0;
+    NodeParams params{};
 };
 
 namespace {
@@ -134,14 +137,7 @@ StepArgs step_args(vplbm_sim s, int src, int t_off)
     a.bx_log2 = s->ts.bx_log2;
     a.by = s->ts.by;
     a.rows = s->ts.rows;
-    a.sp = s->sp;
-    a.sm = s->sm;
-    a.kp = s->kp;
-    a.km = s->km;
-    a.k_relax = s->k_relax;
-    a.c_pen = s->c_pen;
-    a.uin_x = s->cfg.u_in_x;
-    a.uin_y = s->cfg.u_in_y;
+    a.p = s->params;
     return a;
 }
 
@@ -221,6 +217,26 @@ void release(vplbm_sim s)
     delete s;
 }
 
+}  // namespace
+
+namespace vplbm {
+
+NodeParams node_params(const vplbm_config &c)
+{
+    NodeParams p{};
+    // Relaxation: MRT = rates of Eq. 14 (s_n = 1/tau, s_q from Lambda, Eq. 15); SRT = 1/tau.
+    p.sp = 1.0 / c.tau;
+    p.sm = c.collision == VPLBM_MRT ? 1.0 / (0.5 + c.lambda / (c.tau - 0.5)) : p.sp;
+    p.kp = 1.0 - 0.5 * p.sp;
+    p.km = 1.0 - 0.5 * p.sm;
+    // Penalization (Eqs. 17-18, dt = 1): k = 1/(1 + 1/(2 eta)) = 2 eta/(2 eta + 1).
+    p.k_relax = 2.0 * c.eta / (2.0 * c.eta + 1.0);
+    p.c_pen = 1.0 / (c.eta + 0.5);
+    p.uin_x = c.u_in_x;
+    p.uin_y = c.u_in_y;
+    return p;
+}
+
 int check_config(const vplbm_config *c)
 {
     if (!c) return fail(VPLBM_EINVAL, "config is NULL");
@@ -268,7 +284,7 @@ int check_bodies(const vplbm_body *b, int n)
     return VPLBM_OK;
 }
 
-}  // namespace
+}  // namespace vplbm
 
 extern "C" {
 
@@ -293,14 +309,7 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     s->storage = cfg->storage;
     s->ring_len = cfg->ring ? cfg->ring : 4096;
     s->graph_k = graph_chunk();
-    // Relaxation: MRT = rates of Eq. 14 (s_n = 1/tau, s_q from Lambda, Eq. 15); SRT = 1/tau.
-    s->sp = 1.0 / cfg->tau;
-    s->sm = cfg->collision == VPLBM_MRT ? 1.0 / (0.5 + cfg->lambda / (cfg->tau - 0.5)) : s->sp;
-    s->kp = 1.0 - 0.5 * s->sp;
-    s->km = 1.0 - 0.5 * s->sm;
-    // Penalization (Eqs. 17-18, dt = 1): k = 1/(1 + 1/(2 eta)) = 2 eta/(2 eta + 1).
-    s->k_relax = 2.0 * cfg->eta / (2.0 * cfg->eta + 1.0);
-    s->c_pen = 1.0 / (cfg->eta + 0.5);
+    s->params = node_params(*cfg);
 
     Geom &g = s->g;
     g.nx = cfg->nx;

@@ -1,0 +1,105 @@
+"""GPU tests of the serving pool: a request's result is the same alone and in a mix (bitwise),
+equal to the single-simulation path and to the oracle, and admission respects the budget."""
+import numpy as np
+import pytest
+
+from paper_1812_05401_amd import inputs as I
+from tests.helpers import force_scale, oracle_sim, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def small_requests(seed=7, n=6, storage="f64"):
+    r = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        N = int(r.integers(70, 260))
+        M = int(r.integers(40, 200))
+        coll = "mrt" if k % 2 == 0 else "srt"
+        bc = I.CHANNEL if k % 3 != 2 else I.ALL_PERIODIC
+        u_in = (0.04, 0.0) if bc == I.CHANNEL else (0.0, 0.0)
+        u0 = u_in if bc == I.CHANNEL else (0.03, 0.01)    # a periodic box starts with a drift
+        bodies = I.random_bodies(N, M, seed + k, int(r.integers(1, 4)), rmin=3, rmax=min(N, M) / 5)
+        out.append(I.Case(f"pool{k}", N, M, collision=coll, storage=storage,
+                          tau=float(r.uniform(0.55, 0.9)), bc=bc, u_in=u_in, bodies=bodies,
+                          u0=u0, steps=int(r.integers(150, 700))))
+    return out
+
+
+def run(pool_cls, cases, budget, slots=64, spl=32):
+    pool = pool_cls(budget, max_slots=slots, steps_per_launch=spl)
+    ids = [pool.submit(c, c.steps, keep_fields=True) for c in cases]
+    res, max_running = {}, 0
+    while len(res) < len(ids):
+        running, queued, _ = pool.advance()
+        max_running = max(max_running, running)
+        for k, rid in enumerate(ids):
+            if k in res:
+                continue
+            st, _ = pool.status(rid)
+            if st >= 2:
+                res[k] = pool.result(rid, fields=True)
+    pool.close()
+    return res, max_running
+
+
+def test_alone_and_in_the_mix_are_bitwise_equal(gpu):
+    B = gpu
+    cases = small_requests()
+    alone = {k: run(B.Pool, [c], 1 << 30)[0][0] for k, c in enumerate(cases)}
+    # a budget that holds about three of them: admission binds, requests queue and overlap
+    budget = int(3 * max(B.vplbm_pool_bytes_needed(c) for c in cases))
+    mix, max_running = run(B.Pool, cases, budget)
+    assert 1 < max_running < len(cases)
+    for k in range(len(cases)):
+        (oa, fa), (om, fm) = alone[k], mix[k]
+        assert oa["status"] == om["status"] == 0
+        assert oa["step"] == om["step"] == cases[k].steps - 1
+        assert oa["mass"] == om["mass"]
+        assert np.array_equal(oa["fx"], om["fx"]) and np.array_equal(oa["fy"], om["fy"])
+        for a, b in zip(fa, fm):
+            assert np.array_equal(a, b)
+
+
+def test_pool_matches_single_simulation_and_oracle(gpu):
+    B = gpu
+    cases = small_requests(seed=11, n=3)
+    res, _ = run(B.Pool, cases, 1 << 30)
+    for k, c in enumerate(cases):
+        obs, (rho, ux, uy) = res[k]
+        s = B.Simulation(c, stream=None)
+        s.step(c.steps)
+        so, srho, sux, suy = s.observables(fields=True)
+        s.close()
+        assert rel_err(rho, srho) <= 1e-13 and rel_err(np.stack([ux, uy]), np.stack([sux, suy])) <= 1e-12
+        o = oracle_sim(c)
+        o.step(c.steps)
+        oo = o.obs()
+        orho, oux, ouy = o.fields()
+        assert rel_err(rho, orho) <= 1e-12
+        assert rel_err(np.stack([ux, uy]), np.stack([oux, ouy])) <= 1e-12
+        assert abs(obs["mass"] - oo["mass"]) <= 1e-12 * oo["mass"]
+        sc = force_scale(oo)
+        assert np.max(np.abs(obs["fx"] - oo["fx"])) <= 1e-12 * sc
+        assert np.max(np.abs(obs["fy"] - oo["fy"])) <= 1e-12 * sc
+
+
+def test_budget_and_argument_errors(gpu):
+    B = gpu
+    c = small_requests(n=1)[0]
+    need = B.vplbm_pool_bytes_needed(c)
+    pool = B.Pool(need - 1, max_slots=4, steps_per_launch=8)
+    with pytest.raises(B.VplbmError) as e:
+        pool.submit(c)
+    assert e.value.code == B.EBUDGET
+    moving = I.Case("m", 64, 64, bodies=[I.body("disk", 30, 30, r=5, ay=2, freq=0.01)])
+    with pytest.raises(B.VplbmError) as e:
+        pool.submit(moving)
+    assert e.value.code == B.EINVAL
+    pool.close()
+    # one slot: requests run strictly one after another, first come first served
+    cases = small_requests(seed=3, n=3, storage="f32")
+    res, max_running = run(B.Pool, cases, 1 << 30, slots=1)
+    assert max_running == 1 and len(res) == 3
+    for k in range(3):
+        assert res[k][0]["status"] == 0
