@@ -113,6 +113,42 @@ def cpu_baseline(case, steps):
                       f"{case.collision.upper()} in moment space, one thread, {dt:.1f} s"}
 
 
+def serving_leg(n_requests, loads, budget_bytes, fifo_loads):
+    """The serving workload: Poisson arrivals of VP-MRT FP32 channel simulations replayed in real
+    time through the continuous-batching pool at offered loads relative to the measured capacity
+    of the plain FP32 step, beside a one-at-a-time FIFO baseline on the same GPU."""
+    import dataclasses
+    from paper_1812_05401_amd import inputs as I
+    from paper_1812_05401_amd import serve
+    base = I.serving_requests(n=n_requests, rate_per_s=1.0)
+    mean_lups = sum(r.case.nodes * r.case.steps for r in base) / len(base)
+    # capacity of the plain FP32 step on a grid of the mean size of the stream
+    nmean = int(round((sum(r.case.nodes for r in base) / len(base)) ** 0.5 / 32)) * 32
+    probe = I.cylinder_wake(nmean, nmean, d=nmean / 8, x0=nmean / 4, re=200.0, steps=2000)
+    cap = time_workload(probe, 2000, 200)
+    cap_rps = cap["mlups"] * 1e6 / mean_lups
+    out = {"workload": f"serving_{n_requests}_poisson", "requests": n_requests,
+           "mean_lattice_updates_per_request": mean_lups, "budget_bytes": budget_bytes,
+           "plain_fp32_step": {"grid": f"{nmean}x{nmean}", "mlups": round(cap["mlups"], 1)},
+           "capacity_requests_per_s": cap_rps, "runs": {}}
+
+    def at_load(load):
+        rate = load * cap_rps
+        return [dataclasses.replace(r, arrival=r.arrival / rate) for r in base]
+
+    for load in loads:
+        stats, _ = serve.run_pool(at_load(load), budget_bytes, max_slots=128, steps_per_launch=64)
+        out["runs"][f"pool_load_{load}"] = stats
+        print(f"# serving pool load {load}: p50 {stats['p50_s']:.2f} s p99 {stats['p99_s']:.2f} s "
+              f"{stats['aggregate_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    for load in fifo_loads:
+        stats = serve.run_fifo(at_load(load))
+        out["runs"][f"fifo_load_{load}"] = stats
+        print(f"# serving fifo load {load}: p50 {stats['p50_s']:.2f} s p99 {stats['p99_s']:.2f} s "
+              f"{stats['aggregate_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    return out
+
+
 def copy_probe(nbytes, reps):
     import torch
     n = nbytes // 4
@@ -141,6 +177,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 8192 x 2048 objects")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for "
@@ -196,6 +234,8 @@ def main():
             red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "roofline")}
             print(f"# {c.name}/{st}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         line["reduced_precision"] = {"workload": "cylinder_wake_8192x2048", **red}
+    if not args.no_serving:
+        line["serving"] = serving_leg(args.serving_requests, (0.7, 1.2), 2 << 30, (0.7, 1.2))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(I.cylinder_wake_2048x512(), 40)
     print(json.dumps(line), flush=True)

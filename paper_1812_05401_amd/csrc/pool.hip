@@ -1,18 +1,22 @@
 // Serving pool: many resident VP-LBM simulations advanced together by one persistent batched
 // kernel replayed from a captured HIP graph (see the pool section of include/vplbm.h).
 //
-// Device side.  A descriptor per slot (buffers, geometry, parameters, steps done / target) and a
-// table of 64 x 4 tiles covering every resident simulation.  The batched kernel walks the tile
-// table grid-stride; each tile runs the same per-node update as the single-simulation step, so a
-// simulation's fields do not depend on its co-residents.  On a simulation's final step each tile
-// writes its FP64 partial sums (mass, body forces) to its own slot, with a fixed summation order
-// inside the tile; the tick kernel that follows every step folds them in tile order (so the
-// final observables are bitwise independent of the mix) and advances the step counters.
+// Device side.  A descriptor per slot (buffers, geometry, parameters, admission step, target) and
+// a table of 64 x 4 tiles covering every resident simulation.  One workgroup per tile; each tile
+// runs the same per-node update as the single-simulation step, so a simulation's fields do not
+// depend on its co-residents.  All resident simulations advance together, so a simulation's
+// steps done are the pool's step counter (on the device) minus its admission step: no per-step
+// bookkeeping launch is needed.  On a simulation's final step each tile writes its FP64 partial
+// sums (mass, body forces) to its own slot, summed in a fixed order inside the tile; at
+// retirement a fold kernel adds the tiles in tile order, so the final observables are bitwise
+// independent of the mix.
 //
-// Host side.  Between graph replays: retire finished simulations (copy results, free memory),
-// admit queued requests first come first served while the memory budget and slots allow, rebuild
-// the tile table.  The graph itself never changes: it reads the tables from device memory.
+// Host side.  Between graph replays: retire finished simulations (fold, copy results, free
+// memory), admit queued requests first come first served while the memory budget and slots
+// allow, rebuild the tile table.  The graph reads the tables from device memory; it is captured
+// again only when the tile count outgrows its grid.
 #include <math.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <deque>
@@ -40,7 +44,7 @@ struct PoolSim {
     int storage;
     int ntx, ntiles;
     int active;
-    long long done, target;
+    long long t0, target;    // pool step at admission; steps to run
     unsigned status;
     double obs[kRingWidth];  // folded final observables
 };
@@ -63,77 +67,74 @@ __device__ __forceinline__ double pool_node(const PoolSim &d, int parity, int x,
     return double(m.rho);
 }
 
+// One lattice step of every resident simulation: workgroup w (< *ntiles) updates one tile.
 __global__ __launch_bounds__(kBlock) void pool_step_kernel(PoolSim *sims, const TileRef *tiles,
-                                                           const int *ntiles)
+                                                           const int *ntiles,
+                                                           const long long *t_base, int t_off)
 {
     __shared__ double part[kBlock / 64][kRingWidth];
     const int n = *ntiles;
+    if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = xcd_tile(blockIdx.x, gridDim.x); k < n; k += gridDim.x) {
-        const TileRef tr = tiles[k];
-        const PoolSim &d = sims[tr.slot];
-        const long long done = d.done;
-        if (!d.active || done >= d.target) continue;          // uniform over the workgroup
-        const int x = (tr.tile % d.ntx) * kPoolTileW + lane;
-        const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
-        const bool active = (x < d.g.nx) & (y < d.g.ny);
-        const int parity = (int)(done & 1);
-        double rho = 0.0, fx = 0.0, fy = 0.0;
-        int id = 0;
-        if (active) {
-            switch (d.storage) {
-            case kF64: rho = pool_node<kF64>(d, parity, x, y, fx, fy, id); break;
-            case kF32: rho = pool_node<kF32>(d, parity, x, y, fx, fy, id); break;
-            case kF16S: rho = pool_node<kF16S>(d, parity, x, y, fx, fy, id); break;
-            default: rho = pool_node<kBF16S>(d, parity, x, y, fx, fy, id); break;
-            }
+    const TileRef tr = tiles[xcd_tile(blockIdx.x, n)];
+    const PoolSim &d = sims[tr.slot];
+    const long long done = *t_base + t_off - d.t0;
+    if (!d.active || done < 0 || done >= d.target) return;    // uniform over the workgroup
+    const int x = (tr.tile % d.ntx) * kPoolTileW + lane;
+    const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
+    const bool active = (x < d.g.nx) & (y < d.g.ny);
+    const int parity = (int)(done & 1);
+    double rho = 0.0, fx = 0.0, fy = 0.0;
+    int id = 0;
+    if (active) {
+        switch (d.storage) {
+        case kF64: rho = pool_node<kF64>(d, parity, x, y, fx, fy, id); break;
+        case kF32: rho = pool_node<kF32>(d, parity, x, y, fx, fy, id); break;
+        case kF16S: rho = pool_node<kF16S>(d, parity, x, y, fx, fy, id); break;
+        default: rho = pool_node<kBF16S>(d, parity, x, y, fx, fy, id); break;
         }
-        const bool bad = active && !(rho > 0.0 && rho < 1e30);
-        if (__ballot(bad) && lane == 0) atomicOr(&sims[tr.slot].status, 1u);
-        if (done + 1 == d.target) {
-            // Final step: deterministic per-tile sums (wave shuffles, then the four waves in order).
-            if (lane < kRingWidth) part[wave][lane] = 0.0;
-            const double mw = wave_sum(rho);
-            if (lane == 0) part[wave][0] = mw;
-            unsigned long long solid = __ballot(id != 0);
-            while (solid) {
-                const int lead = __ffsll((unsigned long long)solid) - 1;
-                const int b = __shfl(id, lead, 64);
-                const bool mine = id == b;
-                const double sx = wave_sum(mine ? -fx : 0.0);
-                const double sy = wave_sum(mine ? -fy : 0.0);
-                if (lane == 0) {
-                    part[wave][1 + 2 * (b - 1)] = sx;
-                    part[wave][2 + 2 * (b - 1)] = sy;
-                }
-                solid &= ~__ballot(mine);
+    }
+    const bool bad = active && !(rho > 0.0 && rho < 1e30);
+    if (__ballot(bad) && lane == 0) atomicOr(&sims[tr.slot].status, 1u);
+    if (done + 1 == d.target) {
+        // Final step: deterministic per-tile sums (wave shuffles, then the four waves in order).
+        if (lane < kRingWidth) part[wave][lane] = 0.0;
+        const double mw = wave_sum(rho);
+        if (lane == 0) part[wave][0] = mw;
+        unsigned long long solid = __ballot(id != 0);
+        while (solid) {
+            const int lead = __ffsll((unsigned long long)solid) - 1;
+            const int b = __shfl(id, lead, 64);
+            const bool mine = id == b;
+            const double sx = wave_sum(mine ? -fx : 0.0);
+            const double sy = wave_sum(mine ? -fy : 0.0);
+            if (lane == 0) {
+                part[wave][1 + 2 * (b - 1)] = sx;
+                part[wave][2 + 2 * (b - 1)] = sy;
             }
-            __syncthreads();
-            if (threadIdx.x < kRingWidth) {
-                double v = 0.0;
-                for (int w = 0; w < kBlock / 64; w++) v += part[w][threadIdx.x];
-                d.partials[(size_t)tr.tile * kRingWidth + threadIdx.x] = v;
-            }
-            __syncthreads();
+            solid &= ~__ballot(mine);
+        }
+        __syncthreads();
+        if (threadIdx.x < kRingWidth) {
+            double v = 0.0;
+            for (int w = 0; w < kBlock / 64; w++) v += part[w][threadIdx.x];
+            d.partials[(size_t)tr.tile * kRingWidth + threadIdx.x] = v;
         }
     }
 }
 
-// After every batched step: fold the final step's partials (tile order) and count the step.
-__global__ void pool_tick_kernel(PoolSim *sims)
+// Final observables of the simulation in `slot`: its tiles' partial sums added in tile order.
+__global__ void pool_fold_kernel(PoolSim *sims, int slot)
 {
-    PoolSim &d = sims[blockIdx.x];
-    if (!d.active) return;
-    const long long done = d.done;
-    if (done >= d.target) return;
-    if (done + 1 == d.target && threadIdx.x < kRingWidth) {
+    PoolSim &d = sims[slot];
+    if (threadIdx.x < kRingWidth) {
         double v = 0.0;
         for (int t = 0; t < d.ntiles; t++) v += d.partials[(size_t)t * kRingWidth + threadIdx.x];
         d.obs[threadIdx.x] = v;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) d.done = done + 1;
 }
+
+__global__ void pool_advance_kernel(long long *t, long long n) { *t += n; }
 
 }  // namespace vplbm
 
@@ -194,14 +195,17 @@ struct vplbm_pool_s {
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
+    int grid_cap = 0;                     // workgroups per step launch in the captured graph
     PoolSim *d_sims = nullptr;
     TileRef *d_tiles = nullptr;
     int *d_ntiles = nullptr;
+    long long *d_t = nullptr;             // pool step counter (steps every resident sim has run)
     long long *d_zero = nullptr;
     double *staging = nullptr;
     size_t staging_bytes = 0;
     int tile_cap = 0;
-    int grid = 2048;
+    int ntiles = 0;
+    long long t_host = 0;                 // host copy of *d_t after the last finished chunk
     std::vector<PoolSim> h_sims;
     std::vector<int64_t> slot_req;        // request id per slot (-1 free)
     std::map<int64_t, Request> reqs;
@@ -248,36 +252,29 @@ int ensure_pool_staging(vplbm_pool p, size_t bytes)
     return VPLBM_OK;
 }
 
-StepArgs args_for(const PoolSim &d, const Request &r, long long *t_zero)
+long long steps_done(const vplbm_pool p, const PoolSim &d)
 {
-    StepArgs a{};
-    const int parity = (int)(d.done & 1);
-    a.src = d.buf[parity];
-    a.dst = d.buf[parity];
-    a.mask = d.mask;
-    a.bodies = d.bodies;
-    a.t_base = t_zero;
-    a.g = d.g;
-    a.p = d.p;
-    (void)r;
-    return a;
+    const long long n = p->t_host - d.t0;
+    return n < d.target ? n : d.target;
 }
 
-// Copy a finished simulation's results to the host and release its slot and memory.
+// Copy a finished (or failed) simulation's results to the host and release its slot and memory.
 int retire(vplbm_pool p, int slot)
 {
     Request &r = p->reqs[p->slot_req[slot]];
-    const PoolSim &d = p->h_sims[slot];
-    r.done = d.done;
-    r.obs.step = d.done - 1;
-    r.obs.mass = d.obs[0];
-    for (int k = 0; k < kMaxBodies; k++) {
-        r.obs.fx[k] = d.obs[1 + 2 * k];
-        r.obs.fy[k] = d.obs[2 + 2 * k];
-    }
+    PoolSim &d = p->h_sims[slot];
+    const long long done = steps_done(p, d);
+    r.done = done;
+    memset(&r.obs, 0, sizeof r.obs);
+    r.obs.step = done - 1;
     r.obs.nbodies = (int32_t)r.bodies.size();
     r.obs.status = (d.status & 1u) ? 1 : 0;
-    r.state = r.obs.status ? VPLBM_FAILED : VPLBM_DONE;
+    if (done == d.target) {
+        pool_fold_kernel<<<1, 64, 0, p->stream>>>(p->d_sims, slot);
+        HIP_TRY(hipGetLastError());
+        const char *dev_obs = reinterpret_cast<const char *>(p->d_sims + slot) + offsetof(PoolSim, obs);
+        HIP_TRY(hipMemcpyAsync(d.obs, dev_obs, sizeof d.obs, hipMemcpyDeviceToHost, p->stream));
+    }
     if (r.keep_fields) {
         const size_t n = (size_t)d.g.nx * d.g.ny;
         int rc = ensure_pool_staging(p, 3 * n * sizeof(double));
@@ -285,12 +282,27 @@ int retire(vplbm_pool p, int slot)
         r.rho.resize(n);
         r.ux.resize(n);
         r.uy.resize(n);
-        HIP_TRY(launch_readback(d.storage, args_for(d, r, p->d_zero), p->staging, p->staging + n, p->staging + 2 * n, p->stream));
+        StepArgs a{};
+        a.src = d.buf[done & 1];   // the state after `done` steps
+        a.mask = d.mask;
+        a.bodies = d.bodies;
+        a.t_base = p->d_zero;
+        a.g = d.g;
+        a.p = d.p;
+        HIP_TRY(launch_readback(d.storage, a, p->staging, p->staging + n, p->staging + 2 * n, p->stream));
         HIP_TRY(hipMemcpyAsync(r.rho.data(), p->staging, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
         HIP_TRY(hipMemcpyAsync(r.ux.data(), p->staging + n, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
         HIP_TRY(hipMemcpyAsync(r.uy.data(), p->staging + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-        HIP_TRY(hipStreamSynchronize(p->stream));
     }
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if (done == d.target) {
+        r.obs.mass = d.obs[0];
+        for (int k = 0; k < kMaxBodies; k++) {
+            r.obs.fx[k] = d.obs[1 + 2 * k];
+            r.obs.fy[k] = d.obs[2 + 2 * k];
+        }
+    }
+    r.state = r.obs.status ? VPLBM_FAILED : VPLBM_DONE;
     free_request_memory(p, r);
     p->used -= r.bytes;
     r.slot = -1;
@@ -340,7 +352,7 @@ int admit(vplbm_pool p, Request &r, int slot)
     d.p = node_params(r.cfg);
     d.storage = r.cfg.storage;
     d.active = 1;
-    d.done = 0;
+    d.t0 = p->t_host;
     d.target = r.nsteps;
     StepArgs a{};
     a.dst = d.buf[0];
@@ -349,6 +361,8 @@ int admit(vplbm_pool p, Request &r, int slot)
     a.g = d.g;
     a.p = d.p;
     HIP_TRY(launch_init(d.storage, a, nullptr, nullptr, nullptr, r.cfg.rho0, r.cfg.ux0, r.cfg.uy0, p->stream));
+    // the body table copy above reads `hp` from the stack: let it land before returning
+    HIP_TRY(hipStreamSynchronize(p->stream));
     p->h_sims[slot] = d;
     r.slot = slot;
     r.state = VPLBM_RUNNING;
@@ -358,18 +372,26 @@ int admit(vplbm_pool p, Request &r, int slot)
 
 int ensure_pool_graph(vplbm_pool p)
 {
-    if (p->graph) return VPLBM_OK;
+    if (p->graph && p->grid_cap >= p->ntiles && p->grid_cap <= 8 * (p->ntiles > 4096 ? p->ntiles : 4096))
+        return VPLBM_OK;
+    if (p->graph) {
+        HIP_TRY(hipGraphExecDestroy(p->graph));
+        p->graph = nullptr;
+    }
+    int cap = 4096;
+    while (cap < p->ntiles) cap *= 2;
+    p->grid_cap = cap;
     if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int j = 0; j < p->cfg.steps_per_launch && e == hipSuccess; j++) {
-        pool_step_kernel<<<dim3(p->grid), dim3(kBlock), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles);
+        pool_step_kernel<<<dim3(cap), dim3(kBlock), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j);
         e = hipGetLastError();
-        if (e == hipSuccess) {
-            pool_tick_kernel<<<dim3(p->cfg.max_slots), dim3(64), 0, p->cap_stream>>>(p->d_sims);
-            e = hipGetLastError();
-        }
+    }
+    if (e == hipSuccess) {
+        pool_advance_kernel<<<1, 1, 0, p->cap_stream>>>(p->d_t, p->cfg.steps_per_launch);
+        e = hipGetLastError();
     }
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
     if (e != hipSuccess) {
@@ -409,10 +431,11 @@ int upload_tables(vplbm_pool p)
         }
     }
     const int n = (int)tiles.size();
+    p->ntiles = n;
     if (n) HIP_TRY(hipMemcpyAsync(p->d_tiles, tiles.data(), sizeof(TileRef) * n, hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_ntiles, &n, sizeof n, hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_sims, p->h_sims.data(), sizeof(PoolSim) * p->cfg.max_slots, hipMemcpyHostToDevice, p->stream));
-    // The host copies above read pageable memory that changes on the next call: finish them.
+    // The host copies above read memory that changes on the next call: finish them.
     HIP_TRY(hipStreamSynchronize(p->stream));
     return VPLBM_OK;
 }
@@ -456,7 +479,9 @@ int vplbm_pool_create(const vplbm_pool_config *cfg, vplbm_pool *out)
     hipError_t e = hipMalloc(&p->d_sims, sizeof(PoolSim) * cfg->max_slots);
     if (e == hipSuccess) e = hipMalloc(&p->d_ntiles, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&p->d_zero, sizeof(long long));
+    if (e == hipSuccess) e = hipMalloc(&p->d_t, sizeof(long long));
     if (e == hipSuccess) e = hipMemsetAsync(p->d_zero, 0, sizeof(long long), p->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(p->d_t, 0, sizeof(long long), p->stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->d_ntiles, 0, sizeof(int), p->stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->d_sims, 0, sizeof(PoolSim) * cfg->max_slots, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -465,6 +490,7 @@ int vplbm_pool_create(const vplbm_pool_config *cfg, vplbm_pool *out)
         if (p->d_sims) (void)hipFree(p->d_sims);
         if (p->d_ntiles) (void)hipFree(p->d_ntiles);
         if (p->d_zero) (void)hipFree(p->d_zero);
+        if (p->d_t) (void)hipFree(p->d_t);
         if (p->own_stream) (void)hipStreamDestroy(p->stream);
         delete p;
         return fail(VPLBM_ENOMEM, "cannot allocate the pool tables: %s", hipGetErrorString(e));
@@ -512,14 +538,16 @@ int vplbm_pool_advance(vplbm_pool p, int32_t *running, int32_t *queued, int32_t 
     if (p->in_flight) {
         HIP_TRY(hipStreamSynchronize(p->stream));
         p->in_flight = false;
+        p->t_host += p->cfg.steps_per_launch;
         HIP_TRY(hipMemcpy(p->h_sims.data(), p->d_sims, sizeof(PoolSim) * p->cfg.max_slots, hipMemcpyDeviceToHost));
     }
     bool changed = false;
     for (int s = 0; s < p->cfg.max_slots; s++) {
         PoolSim &d = p->h_sims[s];
         if (!d.active) continue;
-        p->reqs[p->slot_req[s]].done = d.done;
-        if (d.done >= d.target || (d.status & 1u)) {
+        const long long done = steps_done(p, d);
+        p->reqs[p->slot_req[s]].done = done;
+        if (done >= d.target || (d.status & 1u)) {
             int rc = retire(p, s);
             if (rc) return rc;
             changed = true;
@@ -592,7 +620,7 @@ int vplbm_pool_destroy(vplbm_pool p)
     for (auto &kv : p->reqs) free_request_memory(p, kv.second);
     (void)hipStreamSynchronize(p->stream);
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
-    void *ptrs[] = {p->d_sims, p->d_tiles, p->d_ntiles, p->d_zero, p->staging};
+    void *ptrs[] = {p->d_sims, p->d_tiles, p->d_ntiles, p->d_zero, p->d_t, p->staging};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
