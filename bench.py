@@ -178,6 +178,13 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the 8192 x 2048 objects")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--precision-study", default="", metavar="WORKLOAD",
+                    help="instead of the benchmark: run WORKLOAD (cylinder_wake_2048x512 or "
+                         "cylinder_wake_8192x2048) in every storage format for --steps steps and "
+                         "print the comparison against FP64")
+    ap.add_argument("--dump", default="", help="with --precision-study: .npz for the series")
+    ap.add_argument("--stats-from", type=int, default=-1,
+                    help="with --precision-study: first step of the statistics window (default: half)")
     ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -197,6 +204,15 @@ def main():
     from paper_1812_05401_amd import binding as B
     from paper_1812_05401_amd import inputs as I
     B.load()
+    if args.precision_study:
+        from paper_1812_05401_amd import study
+        mk = {"cylinder_wake_2048x512": I.cylinder_wake_2048x512,
+              "cylinder_wake_8192x2048": lambda: I.cylinder_wake_8192x2048("f32")}[args.precision_study]
+        res = study.compare_storages(mk(), args.steps, dump=args.dump or None,
+                                     stats_from=None if args.stats_from < 0 else args.stats_from,
+                                     log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+        print(json.dumps(res), flush=True)
+        return
     workloads = {
         "cylinder_wake_2048x512": I.cylinder_wake_2048x512,
         "taylor_couette_128": I.taylor_couette_128,

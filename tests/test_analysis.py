@@ -1,0 +1,48 @@
+"""Host post-processing (Eqs. 20, 22, 23) against closed forms."""
+import math
+
+import numpy as np
+
+from paper_1812_05401_amd import analysis as A
+
+
+def test_strouhal_of_a_pure_sinusoid():
+    u, d, st = 0.05, 64.0, 0.213
+    period = d / (st * u)
+    t = np.arange(60000)
+    cl = 0.7 * np.sin(2 * math.pi * t / period + 0.3) + 0.05
+    assert abs(A.strouhal(cl, d, u) / st - 1) < 1e-4
+    assert A.strouhal(cl[:int(3 * period)], d, u) is None
+
+
+def test_strouhal_ignores_rounding_noise():
+    u, d, st = 0.05, 64.0, 0.2108
+    period = d / (st * u)
+    t = np.arange(50000)
+    r = np.random.default_rng(1)
+    cl = 0.46 * np.sqrt(2) * np.sin(2 * math.pi * t / period) + 0.05 * r.standard_normal(len(t))
+    assert abs(A.strouhal(cl, d, u) / st - 1) < 2e-3
+
+
+def test_force_coefficients_and_statistics():
+    u, d = 0.05, 64.0
+    q = 0.5 * u * u * d
+    t = np.arange(20000)
+    fx = q * (1.3 + 0.01 * np.sin(t / 300))
+    fy = q * 0.9 * math.sqrt(2) * np.sin(2 * math.pi * t / 1000)
+    s = A.wake_statistics(fx, fy, u, d)
+    assert abs(s["C_Dave"] - 1.3) < 1e-3
+    assert abs(s["C_Lrms"] - 0.9) < 1e-3
+    assert abs(s["St"] - d / (1000 * u)) < 1e-6
+
+
+def test_l2_error_matches_definition():
+    r = np.random.default_rng(0)
+    ua = r.normal(size=(5, 7))
+    u = ua + 1e-3 * r.normal(size=(5, 7))
+    w = r.random((5, 7)) < 0.6
+    ref = math.sqrt(np.sum((u - ua)[w] ** 2) / np.sum(ua[w] ** 2))
+    assert abs(A.l2_error(u, ua, w) - ref) < 1e-15
+    v = np.stack([u, 2 * u])
+    va = np.stack([ua, 2 * ua])
+    assert abs(A.l2_error(v, va, w) - ref) < 1e-14

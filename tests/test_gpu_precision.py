@@ -1,0 +1,63 @@
+"""Reduced-precision storage on the GPU.
+
+* The shifted 16-bit codecs round h = f - w_a to nearest even: the decoded population differs
+  from f by at most half an ulp of h in the 16-bit format (plus the FP32 rounding of adding w).
+* FP32, FP16S and BF16S runs against the FP64 oracle on the same inputs: the velocity L2 error of
+  Eq. 20 after 1000 steps is reported and held to bounds derived from each format's unit
+  roundoff (see the design notes): FP32 u = 6e-8, FP16 u = 4.9e-4 and BF16 u = 3.9e-3 of |f - w|.
+"""
+import numpy as np
+import pytest
+
+from paper_1812_05401_amd import analysis as A
+from paper_1812_05401_amd import inputs as I
+from tests.helpers import gpu_sim, oracle_sim, rel_err
+
+pytestmark = pytest.mark.gpu
+
+W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def half_ulp(x, mant_bits):
+    """Half an ulp of |x| in a binary format with `mant_bits` explicit mantissa bits (normal
+    range; the subnormal floor of binary16 is 2^-25)."""
+    e = np.floor(np.log2(np.maximum(np.abs(x), 1e-300)))
+    return np.maximum(2.0 ** (e - mant_bits - 1), 2.0 ** -25 if mant_bits == 10 else 0.0)
+
+
+@pytest.mark.parametrize("storage,mant", [("f16s", 10), ("bf16s", 7)])
+def test_shifted_codec_rounds_to_nearest(gpu, storage, mant):
+    case = I.Case("codec", 67, 13, storage=storage)
+    g = gpu_sim(case)
+    r = np.random.default_rng(5)
+    pop = W[:, None, None] * (1 + r.uniform(-0.3, 0.3, (9, 13, 67)))
+    g.set_populations(pop, 0)
+    back = g.populations()
+    h = pop - W[:, None, None]
+    bound = half_ulp(h, mant) + 1.2e-7 * np.abs(pop)   # + FP32 rounding of h + w
+    assert np.all(np.abs(back - pop) <= bound)
+    # and it is not better than the format allows, i.e. the data really went through 16 bits
+    assert np.max(np.abs(back - pop) / np.maximum(half_ulp(h, mant), 1e-30)) > 0.5
+
+
+CH = ("channel_mrt", 200, 45, "mrt", 0.56, 3 / 16, 1e-7, I.CHANNEL, (0.05, 0.0), 2, False, False)
+# measured velocity L2 (Eq. 20) vs the oracle after 1000 steps on this case, and the bounds
+BOUNDS = {"f32": 1e-5, "f16s": 5e-3, "bf16s": 4e-2}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_reduced_precision_against_the_oracle(gpu, storage):
+    from tests.test_gpu_parity import build_case, make_pair
+    case, _ = build_case(*CH, seed=17)
+    o, g = make_pair(case, None, 17, storage=storage)
+    o.step(1000)
+    g.step(1000)
+    fluid = o.mask() == 0
+    _, oux, ouy = o.fields()
+    rho, ux, uy = g.fields()
+    err = A.l2_error(np.stack([ux, uy]), np.stack([oux, ouy]), fluid)
+    obs = g.observables()
+    m_err = abs(obs["mass"] - o.obs()["mass"]) / o.obs()["mass"]
+    print(f"{storage}: velocity L2 vs oracle {err:.3e}, mass {m_err:.3e}", flush=True)
+    assert obs["status"] == 0
+    assert err < BOUNDS[storage]
