@@ -95,16 +95,19 @@ _lib = None
 
 
 def library_path():
-    return _build.LIB
+    """The in-tree build, or the build named by VPLBM_LIB (another build of the same sources,
+    e.g. for A/B timing of kernel variants)."""
+    return os.environ.get("VPLBM_LIB") or _build.LIB
 
 
 def load():
     """Load libvplbm.so (built in-tree by ``python -m paper_1812_05401_amd.build``)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
-            raise RuntimeError(f"{_build.LIB} is not built: run python -m paper_1812_05401_amd.build")
-        L = C.CDLL(_build.LIB)
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run python -m paper_1812_05401_amd.build")
+        L = C.CDLL(path)
         for name, res, args in SIGNATURES:
             fn = getattr(L, name)
             fn.restype = res

@@ -44,7 +44,7 @@ __device__ __forceinline__ void wave_forces(double *lds_acc, double fx, double f
     }
 }
 
-template <int S>
+template <int S, bool NT>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 {
     using C = Codec<S>;
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if (active) {
-            const Macro<T> m = update_node<S>(src, dst, a.mask, a.bodies, a.g, a.p, x, y, id);
+            const Macro<T> m = update_node<S, NT>(src, dst, a.mask, a.bodies, a.g, a.p, x, y, id);
             const double rho_d = double(m.rho);
             mass += rho_d;
             fx_d = double(m.fx);
@@ -108,7 +108,7 @@ hipError_t launch_fold(const StepArgs &a, hipStream_t st)
 TileShape tile_shape(int nx, int ny, int elem_bytes)
 {
     TileShape t;
-    int bx_log2 = 8;                            // 256 x 1 rows by default
+    int bx_log2 = 7;                            // 128 x 2 by default (measured best)
     while (bx_log2 > 6 && (1 << (bx_log2 - 1)) >= nx) bx_log2--;
     if (const char *e = getenv("VPLBM_TILE_BX_LOG2")) {   // tuning override: 6, 7 or 8
         int v = atoi(e);
@@ -135,13 +135,17 @@ TileShape tile_shape(int nx, int ny, int elem_bytes)
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st)
 {
     const dim3 grid(a.ntx * ((a.g.ny + a.by * a.rows - 1) / (a.by * a.rows))), block(kBlock);
+#define VPLBM_STEP(S)                                                                             \
+    (a.nt_store ? step_kernel<S, true><<<grid, block, 0, st>>>(a)                                   \
+                : step_kernel<S, false><<<grid, block, 0, st>>>(a))
     switch (storage) {
-    case kF64: step_kernel<kF64><<<grid, block, 0, st>>>(a); break;
-    case kF32: step_kernel<kF32><<<grid, block, 0, st>>>(a); break;
-    case kF16S: step_kernel<kF16S><<<grid, block, 0, st>>>(a); break;
-    case kBF16S: step_kernel<kBF16S><<<grid, block, 0, st>>>(a); break;
+    case kF64: VPLBM_STEP(kF64); break;
+    case kF32: VPLBM_STEP(kF32); break;
+    case kF16S: VPLBM_STEP(kF16S); break;
+    case kBF16S: VPLBM_STEP(kBF16S); break;
     default: return hipErrorInvalidValue;
     }
+#undef VPLBM_STEP
     return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ struct StepArgs {
     int ntx;                 // tiles along x
     int bx_log2, by;         // workgroup = (1 << bx_log2) x by threads
     int rows;                // each thread updates `rows` nodes, by rows apart
+    int nt_store;            // 1: non-temporal population stores (buffers larger than the cache)
     NodeParams p;
 };
 

@@ -25,11 +25,14 @@ enum Storage { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
 
 template <int S> struct Codec;
 
+// store_nt: the same value with a non-temporal store, for grids whose buffers do not fit in the
+// Infinity Cache (the next step's reads come from HBM anyway, so the writes need not be cached).
 template <> struct Codec<kF64> {
     using elem = double;
     using real = double;
     static __device__ __forceinline__ real load(const elem *p, int i, real) { return p[i]; }
     static __device__ __forceinline__ void store(elem *p, int i, real v, real) { p[i] = v; }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real) { __builtin_nontemporal_store(v, p + i); }
 };
 
 template <> struct Codec<kF32> {
@@ -37,6 +40,7 @@ template <> struct Codec<kF32> {
     using real = float;
     static __device__ __forceinline__ real load(const elem *p, int i, real) { return p[i]; }
     static __device__ __forceinline__ void store(elem *p, int i, real v, real) { p[i] = v; }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real) { __builtin_nontemporal_store(v, p + i); }
 };
 
 template <> struct Codec<kF16S> {
@@ -44,6 +48,11 @@ template <> struct Codec<kF16S> {
     using real = float;
     static __device__ __forceinline__ real load(const elem *p, int i, real w) { return (float)p[i] + w; }
     static __device__ __forceinline__ void store(elem *p, int i, real v, real w) { p[i] = (_Float16)(v - w); }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real w)
+    {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (_Float16)(v - w)),
+                                    reinterpret_cast<unsigned short *>(p + i));
+    }
 };
 
 template <> struct Codec<kBF16S> {
@@ -51,6 +60,11 @@ template <> struct Codec<kBF16S> {
     using real = float;
     static __device__ __forceinline__ real load(const elem *p, int i, real w) { return (float)p[i] + w; }
     static __device__ __forceinline__ void store(elem *p, int i, real v, real w) { p[i] = (__bf16)(v - w); }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real w)
+    {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (__bf16)(v - w)),
+                                    reinterpret_cast<unsigned short *>(p + i));
+    }
 };
 
 // Lattice weights of Eq. 5 in the compute type.
@@ -252,7 +266,7 @@ struct NodeParams {
 
 // The whole step at node (x, y): pull, edges, moments and penalization, collision, store.
 // Returns the moments (density, penalization force) for the reductions and the body id.
-template <int S>
+template <int S, bool NT = false>
 __device__ __forceinline__ Macro<typename Codec<S>::real>
 update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::elem *__restrict__ dst,
             const uint8_t *__restrict__ mask, const BodyState *__restrict__ bodies, const Geom &g,
@@ -269,9 +283,11 @@ update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::
     if (id) solid_velocity(bodies[id - 1], x, y, usx, usy);
     const Macro<T> m = moments(f, id != 0, usx, usy, T(p.k_relax), T(p.c_pen));
     collide(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));
-    C::store(dst, i, f[0], W<T>::rest);
 #pragma unroll
-    for (int k = 1; k < 9; k++) C::store(dst + k * g.plane, i, f[k], weight<T>(k));
+    for (int k = 0; k < 9; k++) {
+        if (NT) C::store_nt(dst + k * g.plane, i, f[k], weight<T>(k));
+        else C::store(dst + k * g.plane, i, f[k], weight<T>(k));
+    }
     return m;
 }
 
