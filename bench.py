@@ -183,6 +183,8 @@ def main():
                          "cylinder_wake_8192x2048) in every storage format for --steps steps and "
                          "print the comparison against FP64")
     ap.add_argument("--dump", default="", help="with --precision-study: .npz for the series")
+    ap.add_argument("--storages", default="f64,f32,f16s,bf16s",
+                    help="with --precision-study: storage formats to run")
     ap.add_argument("--stats-from", type=int, default=-1,
                     help="with --precision-study: first step of the statistics window (default: half)")
     ap.add_argument("--serving-requests", type=int, default=256)
@@ -207,8 +209,10 @@ def main():
     if args.precision_study:
         from paper_1812_05401_amd import study
         mk = {"cylinder_wake_2048x512": I.cylinder_wake_2048x512,
-              "cylinder_wake_8192x2048": lambda: I.cylinder_wake_8192x2048("f32")}[args.precision_study]
+              "cylinder_wake_8192x2048": lambda: I.cylinder_wake_8192x2048("f32"),
+              "paper_cylinder_re500": I.paper_cylinder_re500}[args.precision_study]
         res = study.compare_storages(mk(), args.steps, dump=args.dump or None,
+                                     storages=tuple(args.storages.split(",")),
                                      stats_from=None if args.stats_from < 0 else args.stats_from,
                                      log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         print(json.dumps(res), flush=True)

@@ -55,9 +55,12 @@ enum vplbm_collision { VPLBM_SRT = 0, VPLBM_MRT = 1 };
 enum vplbm_storage { VPLBM_F64 = 0, VPLBM_F32 = 1, VPLBM_F16S = 2, VPLBM_BF16S = 3 };
 
 /* Edge rules.  x edges: both PERIODIC, or VELOCITY (Zou-He inlet at x = 0 imposing (u_in_x,
-   u_in_y)) with OUTFLOW (zero-gradient outlet at x = nx-1).  y edges: both PERIODIC or both
-   FREESLIP (specular reflection, wall half a link outside the first and last rows). */
-enum vplbm_bc { VPLBM_PERIODIC = 0, VPLBM_VELOCITY = 1, VPLBM_OUTFLOW = 2, VPLBM_FREESLIP = 3 };
+   u_in_y)) with OUTFLOW (zero-gradient outlet at x = nx-1) or CONVECTIVE (the populations
+   entering from x = nx obey df/dt + U df/dx = 0 with U = u_in_x, implicitly upwind: the outlet
+   condition of the paper's cylinder case, Section 3.3).  y edges: both PERIODIC or both FREESLIP
+   (specular reflection, wall half a link outside the first and last rows). */
+enum vplbm_bc { VPLBM_PERIODIC = 0, VPLBM_VELOCITY = 1, VPLBM_OUTFLOW = 2, VPLBM_FREESLIP = 3,
+                VPLBM_CONVECTIVE = 4 };
 
 /* Obstacle shapes; a node belongs to a body when its centre lies inside (boundary included).
    DISK_OUTSIDE is the complement of a disk (|x - c| >= r), e.g. a fixed outer cylinder. */

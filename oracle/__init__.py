@@ -15,7 +15,7 @@ import numpy as np
 from . import build as _build
 
 SRT, MRT = 0, 1
-PERIODIC, VELOCITY, OUTFLOW, FREESLIP = 0, 1, 2, 3
+PERIODIC, VELOCITY, OUTFLOW, FREESLIP, CONVECTIVE = 0, 1, 2, 3, 4
 DISK, RECT, DISK_OUTSIDE = 0, 1, 2
 MAX_BODIES = 8
 

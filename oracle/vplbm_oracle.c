@@ -21,6 +21,12 @@
  *   R5 masks: node-centre inclusion; the lowest-index body containing a node owns it.
  *   R6 force on body k = -(sum over its nodes of the penalization force), i.e. the momentum the
  *      penalization removes from the fluid in that step.
+ *   R7 convective outlet (the paper cites a convective condition whose source is not at hand):
+ *      the unknowns f_a, a in {3, 6, 7}, of the last column obey df/dt + U df/dx = 0 with U the
+ *      inlet speed, discretised implicitly upwind:
+ *        f_a(N-1, t+1) = (f_a(N-1, t) + U f_a(N-2, t+1)) / (1 + U),
+ *      where f(N-2, t+1) is the streamed value of the neighbour column in the same step and
+ *      f(N-1, t) the outlet value of the previous step (the current state's column at start).
  */
 #include "vplbm_oracle.h"
 
@@ -275,7 +281,10 @@ struct orc_sim {
     int moving;
     int64_t n;              /* steps done */
     orc_obs obs;
+    double *prev, *prevn;   /* convective outlet: last column's unknowns 3, 6, 7 ([3][ny]) */
 };
+
+static const int OUTLET_DIRS[3] = {3, 6, 7};   /* populations entering from x = nx */
 
 typedef struct { double s, c; } nsum;   /* Neumaier compensated sum */
 static void nadd(nsum *a, double x)
@@ -294,7 +303,7 @@ orc_sim *orc_create(const orc_config *cfg)
     if (!(cfg->tau > 0.5) || !(cfg->eta > 0.0)) return NULL;
     if (cfg->collision != ORC_SRT && cfg->collision != ORC_MRT) return NULL;
     int xper = cfg->bc_xlo == ORC_PERIODIC && cfg->bc_xhi == ORC_PERIODIC;
-    int xio = cfg->bc_xlo == ORC_VELOCITY && cfg->bc_xhi == ORC_OUTFLOW;
+    int xio = cfg->bc_xlo == ORC_VELOCITY && (cfg->bc_xhi == ORC_OUTFLOW || cfg->bc_xhi == ORC_CONVECTIVE);
     int yper = cfg->bc_ylo == ORC_PERIODIC && cfg->bc_yhi == ORC_PERIODIC;
     int yfs = cfg->bc_ylo == ORC_FREESLIP && cfg->bc_yhi == ORC_FREESLIP;
     if (!(xper || xio) || !(yper || yfs)) return NULL;
@@ -308,6 +317,8 @@ orc_sim *orc_create(const orc_config *cfg)
     s->g = (double *)calloc(9 * N, sizeof(double));
     s->gn = (double *)calloc(9 * N, sizeof(double));
     s->ids = (uint8_t *)calloc(N, 1);
+    s->prev = (double *)calloc(3 * (size_t)cfg->ny, sizeof(double));
+    s->prevn = (double *)calloc(3 * (size_t)cfg->ny, sizeof(double));
     s->n = 0;
     s->obs.step = -1;
     return s;
@@ -319,6 +330,8 @@ void orc_destroy(orc_sim *s)
     free(s->g);
     free(s->gn);
     free(s->ids);
+    free(s->prev);
+    free(s->prevn);
     free(s);
 }
 
@@ -383,6 +396,16 @@ static void solid_velocity(const orc_sim *s, int k, double t, int x, int y, doub
     us[1] = v[1] + om * (x - c[0]);
 }
 
+/* Convective outlet: the previous outlet values start as the state's last column. */
+static void outlet_init(orc_sim *s)
+{
+    int nx = s->cfg.nx, ny = s->cfg.ny;
+    size_t N = (size_t)nx * ny;
+    for (int k = 0; k < 3; k++)
+        for (int y = 0; y < ny; y++)
+            s->prev[k * ny + y] = s->g[OUTLET_DIRS[k] * N + (size_t)y * nx + (nx - 1)];
+}
+
 void orc_init_uniform(orc_sim *s, double rho0, double ux0, double uy0)
 {
     int nx = s->cfg.nx, ny = s->cfg.ny;
@@ -396,6 +419,7 @@ void orc_init_uniform(orc_sim *s, double rho0, double ux0, double uy0)
             orc_feq(rho0, u[0], u[1], feq);
             for (int a = 0; a < 9; a++) s->g[a * N + i] = feq[a];
         }
+    outlet_init(s);
 }
 
 void orc_init_fields(orc_sim *s, const double *rho, const double *ux, const double *uy)
@@ -406,11 +430,13 @@ void orc_init_fields(orc_sim *s, const double *rho, const double *ux, const doub
         orc_feq(rho[i], ux[i], uy[i], feq);
         for (int a = 0; a < 9; a++) s->g[a * N + i] = feq[a];
     }
+    outlet_init(s);
 }
 
 void orc_set_populations(orc_sim *s, const double *pop)
 {
     memcpy(s->g, pop, 9 * sizeof(double) * (size_t)s->cfg.nx * s->cfg.ny);
+    outlet_init(s);
 }
 
 void orc_get_populations(const orc_sim *s, double *pop)
@@ -442,12 +468,25 @@ static double pull(const orc_sim *s, int a, int x, int y)
     return s->g[pa * N + (size_t)sy * nx + sx];
 }
 
+/* Streamed populations at node (x, y) with every edge rule applied (reading R4, R7). */
+static void stream_node(const orc_sim *s, int x, int y, double f[9])
+{
+    for (int a = 0; a < 9; a++) f[a] = pull(s, a, x, y);
+    if (x == s->cfg.nx - 1 && s->cfg.bc_xhi == ORC_CONVECTIVE) {
+        double U = s->cfg.u_in_x;
+        for (int k = 0; k < 3; k++) {
+            int a = OUTLET_DIRS[k];
+            f[a] = (s->prev[k * s->cfg.ny + y] + U * pull(s, a, s->cfg.nx - 2, y)) / (1.0 + U);
+        }
+    }
+    if (x == 0 && s->cfg.bc_xlo == ORC_VELOCITY) orc_zou_he_inlet(f, s->cfg.u_in_x, s->cfg.u_in_y);
+}
+
 /* Front half of a step at node (x, y) and time t: stream, edges, moments and penalization. */
 static void node_macros(const orc_sim *s, int x, int y, double t, double f[9],
                         double *rho, double u[2], double fpen[2], int *id)
 {
-    for (int a = 0; a < 9; a++) f[a] = pull(s, a, x, y);
-    if (x == 0 && s->cfg.bc_xlo == ORC_VELOCITY) orc_zou_he_inlet(f, s->cfg.u_in_x, s->cfg.u_in_y);
+    stream_node(s, x, y, f);
     *id = s->ids[(size_t)y * s->cfg.nx + x];
     double us[2] = {0.0, 0.0};
     if (*id) solid_velocity(s, *id - 1, t, x, y, us);
@@ -456,8 +495,7 @@ static void node_macros(const orc_sim *s, int x, int y, double t, double f[9],
 
 void orc_pull_node(const orc_sim *s, int32_t x, int32_t y, double f[9])
 {
-    for (int a = 0; a < 9; a++) f[a] = pull(s, a, x, y);
-    if (x == 0 && s->cfg.bc_xlo == ORC_VELOCITY) orc_zou_he_inlet(f, s->cfg.u_in_x, s->cfg.u_in_y);
+    stream_node(s, x, y, f);
 }
 
 void orc_step(orc_sim *s, int64_t nsteps)
@@ -480,6 +518,8 @@ void orc_step(orc_sim *s, int64_t nsteps)
                 else orc_collide_mrt(f, rho, u, fpen, s->s, out);
                 size_t i = (size_t)y * nx + x;
                 for (int a = 0; a < 9; a++) s->gn[a * N + i] = out[a];
+                if (x == nx - 1)
+                    for (int k = 0; k < 3; k++) s->prevn[k * ny + y] = f[OUTLET_DIRS[k]];
                 nadd(&mass, rho);
                 if (id) {
                     nadd(&fx[id - 1], -fpen[0]);
@@ -488,6 +528,7 @@ void orc_step(orc_sim *s, int64_t nsteps)
                 }
             }
         double *tmp = s->g; s->g = s->gn; s->gn = tmp;
+        tmp = s->prev; s->prev = s->prevn; s->prevn = tmp;
         s->obs.step = s->n;
         s->obs.mass = nval(mass);
         s->obs.nbodies = s->nb;

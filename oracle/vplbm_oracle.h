@@ -25,7 +25,7 @@ extern "C" {
 #endif
 
 enum { ORC_SRT = 0, ORC_MRT = 1 };
-enum { ORC_PERIODIC = 0, ORC_VELOCITY = 1, ORC_OUTFLOW = 2, ORC_FREESLIP = 3 };
+enum { ORC_PERIODIC = 0, ORC_VELOCITY = 1, ORC_OUTFLOW = 2, ORC_FREESLIP = 3, ORC_CONVECTIVE = 4 };
 enum { ORC_DISK = 0, ORC_RECT = 1, ORC_DISK_OUTSIDE = 2 };
 #define ORC_MAX_BODIES 8
 
@@ -36,7 +36,8 @@ typedef struct {
     double lambda;              /* MRT magic parameter Lambda (Eq. 15); s_n = 1/tau */
     double eta;                 /* penalization parameter (Eq. 17) */
     int32_t bc_xlo, bc_xhi, bc_ylo, bc_yhi;
-    double u_in_x, u_in_y;      /* velocity imposed by the inlet rule on x = 0 */
+    double u_in_x, u_in_y;      /* velocity imposed by the inlet rule on x = 0; u_in_x is also the
+                                   convection speed of a convective outlet */
     int32_t use_rates;          /* MRT only: 1 = take the nine rates from rates[] instead of Eq. 14 */
     double rates[9];
 } orc_config;

@@ -20,12 +20,13 @@ RING_WIDTH = 1 + 2 * MAX_BODIES
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, EBUDGET, ESTATE = 0, -1, -2, -3, -4, -5, -6
 SRT, MRT = 0, 1
 F64, F32, F16S, BF16S = 0, 1, 2, 3
-PERIODIC, VELOCITY, OUTFLOW, FREESLIP = 0, 1, 2, 3
+PERIODIC, VELOCITY, OUTFLOW, FREESLIP, CONVECTIVE = 0, 1, 2, 3, 4
 DISK, RECT, DISK_OUTSIDE = 0, 1, 2
 
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
 COLLISION = {"srt": SRT, "mrt": MRT}
-BC = {"periodic": PERIODIC, "velocity": VELOCITY, "outflow": OUTFLOW, "freeslip": FREESLIP}
+BC = {"periodic": PERIODIC, "velocity": VELOCITY, "outflow": OUTFLOW, "freeslip": FREESLIP,
+      "convective": CONVECTIVE}
 SHAPE = {"disk": DISK, "rect": RECT, "disk_outside": DISK_OUTSIDE}
 
 

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if (active) {
-            const Macro<T> m = update_node<S, NT>(src, dst, a.mask, a.bodies, a.g, a.p, x, y, id);
+            const Macro<T> m = update_node<S, NT>(src, dst, a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id);
             const double rho_d = double(m.rho);
             mass += rho_d;
             fx_d = double(m.fx);
@@ -162,7 +162,8 @@ __global__ __launch_bounds__(kBlock) void readback_kernel(StepArgs a, double *rh
     if (node >= a.g.nx * a.g.ny) return;
     const int x = node % a.g.nx, y = node / a.g.nx;
     T f[9];
-    pull<S>(static_cast<const E *>(a.src), x, y, a.g, f);
+    const Outlet o{a.outlet.prev, nullptr, a.outlet.u};   // observe only: do not record
+    pull<S>(static_cast<const E *>(a.src), x, y, a.g, o, f);
     if (a.g.inlet && x == 0) zou_he_west(f, T(a.p.uin_x), T(a.p.uin_y));
     const int id = a.mask[y * a.g.pitch + x];
     T usx = T(0), usy = T(0);
@@ -274,6 +275,29 @@ hipError_t launch_decode(int storage, const StepArgs &a, double *pop, hipStream_
 {
     const dim3 grid = node_grid(a.g), block(kBlock);
     VPLBM_DISPATCH(storage, decode_kernel, a, pop);
+    return hipGetLastError();
+}
+
+template <int S>
+__global__ void outlet_init_kernel(StepArgs a, void *prev)
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    using E = typename C::elem;
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.g.ny) return;
+    constexpr int dirs[3] = {3, 6, 7};
+    const E *src = static_cast<const E *>(a.src);
+    T *p = static_cast<T *>(prev);
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        p[k * a.g.ny + y] = C::load(src + dirs[k] * a.g.plane, y * a.g.pitch + a.g.nx - 1, weight<T>(dirs[k]));
+}
+
+hipError_t launch_outlet_init(int storage, const StepArgs &a, void *prev, hipStream_t st)
+{
+    const dim3 grid((a.g.ny + 255) / 256), block(256);
+    VPLBM_DISPATCH(storage, outlet_init_kernel, a, prev);
     return hipGetLastError();
 }
 

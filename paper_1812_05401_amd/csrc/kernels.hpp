@@ -33,6 +33,7 @@ struct StepArgs {
     unsigned *status;        // bit 0: non-finite or non-positive density seen
     const long long *t_base; // step counter on the device
     Geom g;
+    Outlet outlet;           // convective outlet state (prev = nullptr: none)
     int t_off;               // this launch's step = *t_base + t_off
     int ring_len;
     int reduce;              // 1: accumulate mass and body forces into the ring
@@ -73,6 +74,8 @@ hipError_t launch_mask(uint8_t *mask, const Geom &g, const BodyParams *params,
                        hipStream_t st);
 
 hipError_t launch_advance(long long *t_base, long long n, hipStream_t st);
+// Convective outlet: prev = the last column's populations 3, 6, 7 of the state a.src.
+hipError_t launch_outlet_init(int storage, const StepArgs &a, void *prev, hipStream_t st);
 // Sum the sub-slots of step *t_base - 1 into its ring entry (without clearing them).
 hipError_t launch_fold(const StepArgs &a, hipStream_t st);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);

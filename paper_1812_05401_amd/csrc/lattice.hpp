@@ -85,7 +85,16 @@ struct Geom {
     int nx, ny, pitch;      // pitch: elements per row (>= nx, multiple of 64)
     int plane;              // elements per population plane
     int xper, yper;         // periodic x / y
-    int inlet;              // Zou-He velocity inlet on x = 0 (then x = nx-1 is a zero-gradient outlet)
+    int inlet;              // Zou-He velocity inlet on x = 0 (then x = nx-1 is an outlet)
+};
+
+// Convective outlet on x = nx-1: the populations entering from x = nx (3, 6, 7) obey
+// df/dt + U df/dx = 0, implicitly upwind: f(nx-1, t+1) = (f(nx-1, t) + U f(nx-2, t+1)) / (1 + U).
+// prev holds f(nx-1, t) as [3][ny] in the compute type; the step writes next (the other parity).
+struct Outlet {
+    const void *prev;       // nullptr: zero-gradient outlet (or no outlet)
+    void *next;             // nullptr: do not record (observation kernels)
+    double u;               // convection speed
 };
 
 // Source of direction a at edge node (x, y) under the edge rules: a row outside the lattice
@@ -114,7 +123,7 @@ __device__ __forceinline__ int edge_source(int a, int x, int y, const Geom &g, i
 // Pull the nine populations of node (x, y) from the post-collision planes `src`.
 template <int S>
 __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__ src, int x, int y,
-                                     const Geom &g, typename Codec<S>::real f[9])
+                                     const Geom &g, const Outlet &o, typename Codec<S>::real f[9])
 {
     using C = Codec<S>;
     using T = typename C::real;
@@ -137,6 +146,24 @@ __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__
             int pa;
             int j = edge_source(a, x, y, g, pa);
             f[a] = C::load(src + pa * g.plane, j, weight<T>(a));
+        }
+        if (o.prev && x == g.nx - 1) {
+            constexpr int dirs[3] = {3, 6, 7};
+            const T *prev = static_cast<const T *>(o.prev);
+            const T u = T(o.u);
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const int a = dirs[k];
+                int pa;
+                const int j = edge_source(a, g.nx - 2, y, g, pa);
+                const T nb = C::load(src + pa * g.plane, j, weight<T>(a));
+                f[a] = (prev[k * g.ny + y] + u * nb) / (T(1) + u);
+            }
+            if (o.next) {
+                T *next = static_cast<T *>(o.next);
+#pragma unroll
+                for (int k = 0; k < 3; k++) next[k * g.ny + y] = f[dirs[k]];
+            }
         }
     }
 }
@@ -270,12 +297,12 @@ template <int S, bool NT = false>
 __device__ __forceinline__ Macro<typename Codec<S>::real>
 update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::elem *__restrict__ dst,
             const uint8_t *__restrict__ mask, const BodyState *__restrict__ bodies, const Geom &g,
-            const NodeParams &p, int x, int y, int &id)
+            const Outlet &o, const NodeParams &p, int x, int y, int &id)
 {
     using C = Codec<S>;
     using T = typename C::real;
     T f[9];
-    pull<S>(src, x, y, g, f);
+    pull<S>(src, x, y, g, o, f);
     if (g.inlet && x == 0) zou_he_west(f, T(p.uin_x), T(p.uin_y));
     const int i = y * g.pitch + x;
     id = mask[i];

@@ -61,7 +61,8 @@ __device__ __forceinline__ double pool_node(const PoolSim &d, int parity, int x,
     using E = typename C::elem;
     const E *src = static_cast<const E *>(d.buf[parity]);
     E *dst = static_cast<E *>(d.buf[parity ^ 1]);
-    const auto m = update_node<S>(src, dst, d.mask, d.bodies, d.g, d.p, x, y, id);
+    const Outlet none{nullptr, nullptr, 0.0};
+    const auto m = update_node<S>(src, dst, d.mask, d.bodies, d.g, none, d.p, x, y, id);
     fx = double(m.fx);
     fy = double(m.fy);
     return double(m.rho);
@@ -516,6 +517,7 @@ int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *b
         if (bodies[k].freq != 0.0 && (bodies[k].ax != 0.0 || bodies[k].ay != 0.0))
             return fail(VPLBM_EINVAL, "pool simulations take static bodies only (body %d moves)", k);
     if (nsteps < 1) return fail(VPLBM_EINVAL, "nsteps must be >= 1");
+    if (cfg->bc_xhi == VPLBM_CONVECTIVE) return fail(VPLBM_EINVAL, "pool simulations take the zero-gradient outlet, not the convective one");
     const uint64_t need = bytes_needed(*cfg);
     if (need > p->cfg.budget_bytes)
         return fail(VPLBM_EBUDGET, "simulation needs %llu bytes, pool budget is %llu", (unsigned long long)need, (unsigned long long)p->cfg.budget_bytes);

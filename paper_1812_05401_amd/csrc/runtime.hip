@@ -87,6 +87,7 @@ struct vplbm_sim_s {
     unsigned *status = nullptr;
     long long *t_dev = nullptr;
     double *staging = nullptr;          // dense FP64 host<->device staging
+    void *outlet[2] = {nullptr, nullptr}; // convective outlet state per buffer parity
     size_t staging_bytes = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -131,6 +132,9 @@ StepArgs step_args(vplbm_sim s, int src, int t_off)
     a.status = s->status;
     a.t_base = s->t_dev;
     a.g = s->g;
+    a.outlet.prev = s->outlet[src];
+    a.outlet.next = s->outlet[src ^ 1];
+    a.outlet.u = s->cfg.u_in_x;
     a.t_off = t_off;
     a.ring_len = s->ring_len;
     a.reduce = s->cfg.reduce;
@@ -155,6 +159,13 @@ hipError_t place_bodies(vplbm_sim s, int t_off, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Convective outlet: the previous-step outlet values start as the current state's last column.
+hipError_t reset_outlet(vplbm_sim s)
+{
+    if (!s->outlet[0]) return hipSuccess;
+    return launch_outlet_init(s->storage, step_args(s, s->cur, 0), s->outlet[s->cur], s->stream);
 }
 
 hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st)
@@ -210,7 +221,7 @@ void release(vplbm_sim s)
     for (int p = 0; p < 2; p++)
         if (s->graph[p]) (void)hipGraphExecDestroy(s->graph[p]);
     void *ptrs[] = {s->buf[0], s->buf[1], s->mask, s->d_params, s->d_state, s->ring, s->acc,
-                    s->status, s->t_dev, s->staging};
+                    s->status, s->t_dev, s->staging, s->outlet[0], s->outlet[1]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -257,13 +268,15 @@ int check_config(const vplbm_config *c)
     if (!(c->eta > 0) || !isfinite(c->eta)) return fail(VPLBM_EINVAL, "eta must be > 0 (got %g)", c->eta);
     if (!(c->rho0 > 0) || !isfinite(c->rho0)) return fail(VPLBM_EINVAL, "rho0 must be > 0");
     const bool xper = c->bc_xlo == VPLBM_PERIODIC && c->bc_xhi == VPLBM_PERIODIC;
-    const bool xio = c->bc_xlo == VPLBM_VELOCITY && c->bc_xhi == VPLBM_OUTFLOW;
+    const bool xio = c->bc_xlo == VPLBM_VELOCITY && (c->bc_xhi == VPLBM_OUTFLOW || c->bc_xhi == VPLBM_CONVECTIVE);
     const bool yper = c->bc_ylo == VPLBM_PERIODIC && c->bc_yhi == VPLBM_PERIODIC;
     const bool yfs = c->bc_ylo == VPLBM_FREESLIP && c->bc_yhi == VPLBM_FREESLIP;
     if (!(xper || xio))
-        return fail(VPLBM_EINVAL, "x edges must be PERIODIC/PERIODIC or VELOCITY/OUTFLOW (got %d/%d)", c->bc_xlo, c->bc_xhi);
+        return fail(VPLBM_EINVAL, "x edges must be PERIODIC/PERIODIC or VELOCITY/OUTFLOW|CONVECTIVE (got %d/%d)", c->bc_xlo, c->bc_xhi);
     if (!(yper || yfs))
         return fail(VPLBM_EINVAL, "y edges must be PERIODIC/PERIODIC or FREESLIP/FREESLIP (got %d/%d)", c->bc_ylo, c->bc_yhi);
+    if (c->bc_xhi == VPLBM_CONVECTIVE && !(c->u_in_x > 0.0))
+        return fail(VPLBM_EINVAL, "a convective outlet needs a positive convection speed u_in_x");
     if (xio && !(fabs(c->u_in_x) < 1.0 && isfinite(c->u_in_y)))
         return fail(VPLBM_EINVAL, "inlet velocity must satisfy |u_in_x| < 1");
     if (c->reduce != 0 && c->reduce != 1) return fail(VPLBM_EINVAL, "reduce must be 0 or 1");
@@ -347,8 +360,11 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
         {(void **)&s->acc, sizeof(double) * 2 * kSub * kRingWidth},
         {(void **)&s->status, sizeof(unsigned) * 4},
         {(void **)&s->t_dev, sizeof(long long)},
+        {&s->outlet[0], cfg->bc_xhi == VPLBM_CONVECTIVE ? sizeof(double) * 3 * g.ny : 0},
+        {&s->outlet[1], cfg->bc_xhi == VPLBM_CONVECTIVE ? sizeof(double) * 3 * g.ny : 0},
     };
     for (auto &a : allocs) {
+        if (a.n == 0) continue;
         if (hipMalloc(a.p, a.n) != hipSuccess) {
             (void)hipGetLastError();
             size_t need = a.n;
@@ -367,11 +383,12 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     if (e == hipSuccess) e = hipMemsetAsync(s->buf[0], 0, s->buf_bytes, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->buf[1], 0, s->buf_bytes, s->stream);
     if (e == hipSuccess) e = launch_init(s->storage, step_args(s, 1, 0), nullptr, nullptr, nullptr, cfg->rho0, cfg->ux0, cfg->uy0, s->stream);
+    s->cur = 0;
+    if (e == hipSuccess) e = reset_outlet(s);
     if (e != hipSuccess) {
         release(s);
         return fail(VPLBM_EHIP, "initialisation failed: %s", hipGetErrorString(e));
     }
-    s->cur = 0;
     track(s, true);
     *out = s;
     return VPLBM_OK;
@@ -442,8 +459,10 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
     } else {
         HIP_TRY(launch_mask(s->mask, g, s->d_params, s->d_state, nbodies, 0, 0, g.nx, g.ny, s->stream));
     }
-    if (s->steps == 0)
+    if (s->steps == 0) {
         HIP_TRY(launch_init(s->storage, step_args(s, s->cur ^ 1, 0), nullptr, nullptr, nullptr, s->cfg.rho0, s->cfg.ux0, s->cfg.uy0, s->stream));
+        HIP_TRY(reset_outlet(s));
+    }
     HIP_TRY(hipStreamSynchronize(s->stream));   // body_id / bodies may be freed by the caller
     return VPLBM_OK;
 }
@@ -519,6 +538,7 @@ int vplbm_init_fields(vplbm_sim s, const double *rho, const double *ux, const do
     HIP_TRY(hipMemcpyAsync(s->staging + n, ux, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->staging + 2 * n, uy, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_init(s->storage, step_args(s, s->cur ^ 1, 0), s->staging, s->staging + n, s->staging + 2 * n, 0, 0, 0, s->stream));
+    HIP_TRY(reset_outlet(s));
     HIP_TRY(hipStreamSynchronize(s->stream));
     return VPLBM_OK;
 }
@@ -544,6 +564,7 @@ int vplbm_set_populations(vplbm_sim s, const double *pop, int64_t step)
     if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(s->staging, pop, 9 * n * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_encode(s->storage, step_args(s, s->cur ^ 1, 0), s->staging, s->stream));
+    HIP_TRY(reset_outlet(s));
     long long t = step;
     HIP_TRY(hipMemcpyAsync(s->t_dev, &t, sizeof t, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_fill_f64(s->acc, (size_t)2 * kSub * kRingWidth, 0.0, s->stream));

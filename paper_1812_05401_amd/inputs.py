@@ -18,7 +18,9 @@ import numpy as np
 
 SRT, MRT = "srt", "mrt"
 PERIODIC, VELOCITY, OUTFLOW, FREESLIP = "periodic", "velocity", "outflow", "freeslip"
+CONVECTIVE = "convective"
 CHANNEL = (VELOCITY, OUTFLOW, FREESLIP, FREESLIP)
+CHANNEL_CONVECTIVE = (VELOCITY, CONVECTIVE, FREESLIP, FREESLIP)
 ALL_PERIODIC = (PERIODIC, PERIODIC, PERIODIC, PERIODIC)
 GINZBURG_LAMBDA = 3.0 / 16.0   # Section 2.1.2: the value used with s_n = 1/tau
 
@@ -99,6 +101,17 @@ def oscillating_cylinder_8192x2048(steps=200_000) -> Case:
     c.name = "oscillating_cylinder_8192x2048"
     c.bodies = [body("disk", 1024.0, 1024.0, r=d / 2.0, ay=0.2 * d, freq=0.2 * u / d)]
     return c
+
+
+def paper_cylinder_re500(storage="f32", steps=500_000) -> Case:
+    """The paper's bluff-body case (Section 3.3): a 30 D x 10 D channel resolved by 6048 x 2016
+    nodes, D = 201 nodes, the cylinder 25 D from the outlet, inlet speed 0.05, SRT tau = 0.56
+    (Re = 0.05 * 201 / ((0.56 - 1/2)/3) = 502.5), symmetry (free-slip) planes above and below,
+    convective outlet, eta = 1e-7.  The centre sits at y = ny/2, half a node off the mid-plane."""
+    nx, ny, d = 6048, 2016, 201.0
+    return Case("paper_cylinder_re500", nx, ny, collision=SRT, storage=storage, tau=0.56, eta=1e-7,
+                bc=CHANNEL_CONVECTIVE, u_in=(0.05, 0.0), u0=(0.05, 0.0),
+                bodies=[body("disk", nx - 25 * d, ny / 2.0, r=d / 2.0)], steps=steps, diameter=d)
 
 
 # ---- random inputs for parity tests ---------------------------------------------------------

@@ -6,7 +6,7 @@ from paper_1812_05401_amd import inputs as I
 
 ORC_COLL = {I.SRT: O.SRT, I.MRT: O.MRT}
 ORC_BC = {I.PERIODIC: O.PERIODIC, I.VELOCITY: O.VELOCITY, I.OUTFLOW: O.OUTFLOW,
-          I.FREESLIP: O.FREESLIP}
+          I.FREESLIP: O.FREESLIP, I.CONVECTIVE: O.CONVECTIVE}
 ORC_KIND = {"disk": O.DISK, "rect": O.RECT, "disk_outside": O.DISK_OUTSIDE}
 
 

@@ -57,6 +57,7 @@ BAD = [
     (dict(nx=10, ny=10, bc=("periodic", "periodic", "freeslip", "periodic")), "y edges"),
     (dict(nx=10, ny=10, bc=("velocity", "outflow", "freeslip", "freeslip"), u_in=(1.5, 0)), "inlet"),
     (dict(nx=10, ny=10, ring=1), "ring"),
+    (dict(nx=10, ny=10, bc=("velocity", "convective", "freeslip", "freeslip")), "convection speed"),
     (dict(nx=100000, ny=100000), "too large"),
 ]
 

@@ -32,6 +32,8 @@ CASES = [
     ("tiny_channel", 5, 4, "srt", 0.7, 3 / 16, 1e-7, CH, (0.03, 0.0), 0, False, False),
     ("wide_ragged", 517, 9, "mrt", 0.7, 3 / 16, 1e-7, PFS, (0.0, 0.0), 2, False, False),
     ("tall_ragged", 65, 300, "srt", 0.9, 3 / 16, 1e-7, CH, (0.05, 0.0), 2, False, False),
+    ("convective_srt", 150, 40, "srt", 0.56, 3 / 16, 1e-7, I.CHANNEL_CONVECTIVE, (0.05, 0.0), 2, False, False),
+    ("convective_mrt_moving", 150, 40, "mrt", 0.6, 3 / 16, 1e-7, I.CHANNEL_CONVECTIVE, (0.04, 0.0), 2, True, False),
 ]
 
 
@@ -189,4 +191,20 @@ def test_full_size_cylinder_2048x512(gpu):
     g32.step(40)
     eg, er, eu, em, ef = compare(o, g32, 0, "cylinder_2048x512_f32")
     # FP32: a few roundings of ~6e-8 per step on populations of size <= 0.45
+    assert eg < 1e-5 and er < 1e-5 and eu < 1e-4 and em < 1e-6 and ef < 1e-4
+
+
+def test_full_size_paper_cylinder_re500(gpu):
+    """The paper's 6048 x 2016 Re = 500 case (SRT, convective outlet) at its full size, 3 steps
+    from the uniform start, FP64 and FP32 storage against the oracle."""
+    case = I.paper_cylinder_re500()
+    o = oracle_sim(case)
+    o.step(3)
+    g64 = gpu_sim(case, storage="f64")
+    g64.step(3)
+    assert max(compare(o, g64, TOL64, "paper_cylinder_f64")) <= TOL64
+    g64.close()
+    g32 = gpu_sim(case, storage="f32")
+    g32.step(3)
+    eg, er, eu, em, ef = compare(o, g32, 0, "paper_cylinder_f32")
     assert eg < 1e-5 and er < 1e-5 and eu < 1e-4 and em < 1e-6 and ef < 1e-4

@@ -249,3 +249,38 @@ def test_rigid_rotation_is_counter_clockwise_for_positive_omega():
     rho, ux, uy = s.fields()
     assert abs(uy[15, 20] - 0.002 * 5) < 1e-9 and abs(ux[15, 20] - 0.001) < 1e-9
     assert abs(ux[20, 15] - (0.001 - 0.002 * 5)) < 1e-9 and abs(uy[20, 15]) < 1e-9
+
+
+def test_uniform_channel_flow_is_a_fixed_point_of_the_convective_outlet():
+    U = 0.05
+    for coll in (O.SRT, O.MRT):
+        s = O.OracleSim(31, 17, coll, tau=0.56, bc=(O.VELOCITY, O.CONVECTIVE, O.FREESLIP, O.FREESLIP),
+                        u_in=(U, 0.0))
+        s.init_uniform(1.0, U, 0.0)
+        g0 = s.populations()
+        s.step(40)
+        assert rel_err(s.populations(), g0) < 100 * EPS
+
+
+def test_convective_outlet_advances_in_time_with_the_inlet_speed():
+    """Reading R7: (1 + U) f(N-1, t+1) = f(N-1, t) + U f(N-2, t+1) for the unknowns 3, 6, 7, each
+    value taken from consecutive steps, i.e. df/dt + U df/dx = 0 implicitly upwind; the other
+    six populations of the column are plainly streamed."""
+    nx, ny, U = 30, 12, 0.05
+    s, _ = _random_sim(nx, ny, 12, O.MRT, bc=(O.VELOCITY, O.CONVECTIVE, O.FREESLIP, O.FREESLIP),
+                       nb=2, u_in=(U, 0.0))
+    s.step(15)
+    before = [s.pull_node(nx - 1, y) for y in range(ny)]
+    s.step(1)
+    for y in range(ny):
+        now = s.pull_node(nx - 1, y)
+        nb = s.pull_node(nx - 2, y)
+        for a in (3, 6, 7):
+            assert abs((1 + U) * now[a] - before[y][a] - U * nb[a]) < 4 * EPS
+    z = O.OracleSim(nx, ny, O.MRT, tau=0.7, bc=(O.VELOCITY, O.OUTFLOW, O.FREESLIP, O.FREESLIP), u_in=(U, 0.0))
+    z.set_populations(s.populations())
+    for y in range(ny):
+        f = s.pull_node(nx - 1, y)
+        g = z.pull_node(nx - 1, y)
+        for a in (0, 1, 2, 4, 5, 8):
+            assert f[a] == g[a]
