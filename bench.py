@@ -183,6 +183,11 @@ def main():
                          "cylinder_wake_8192x2048) in every storage format for --steps steps and "
                          "print the comparison against FP64")
     ap.add_argument("--dump", default="", help="with --precision-study: .npz for the series")
+    ap.add_argument("--sweep", default="", choices=["", "fig3", "fig12", "table1"],
+                    help="instead of the benchmark: run one of the paper's parameter sweeps "
+                         "through the serving pool and print the L2 errors")
+    ap.add_argument("--me-every", type=int, default=0,
+                    help="with --precision-study: sample the momentum-exchange force every N steps")
     ap.add_argument("--storages", default="f64,f32,f16s,bf16s",
                     help="with --precision-study: storage formats to run")
     ap.add_argument("--stats-from", type=int, default=-1,
@@ -206,6 +211,19 @@ def main():
     from paper_1812_05401_amd import binding as B
     from paper_1812_05401_amd import inputs as I
     B.load()
+    if args.sweep:
+        from paper_1812_05401_amd import sweeps
+        pts = {"fig3": sweeps.fig3_shear, "fig12": sweeps.fig12_couette,
+               "table1": sweeps.table1_grids}[args.sweep]()
+        t0 = time.perf_counter()
+        res = sweeps.run(pts)
+        wall = time.perf_counter() - t0
+        lups = sum(p.case.nodes * p.case.steps for p in pts)
+        print(json.dumps({"sweep": args.sweep, "points": len(pts), "lattice_updates": lups,
+                          "wall_s": wall, "mlups": lups / wall / 1e6,
+                          "results": [{"label": l, **prm, "l2_error": e, "status": st}
+                                      for l, prm, e, st in res]}), flush=True)
+        return
     if args.precision_study:
         from paper_1812_05401_amd import study
         mk = {"cylinder_wake_2048x512": I.cylinder_wake_2048x512,
@@ -213,6 +231,7 @@ def main():
               "paper_cylinder_re500": I.paper_cylinder_re500}[args.precision_study]
         res = study.compare_storages(mk(), args.steps, dump=args.dump or None,
                                      storages=tuple(args.storages.split(",")),
+                                     me_every=args.me_every,
                                      stats_from=None if args.stats_from < 0 else args.stats_from,
                                      log=lambda m: print("# " + m, file=sys.stderr, flush=True))
         print(json.dumps(res), flush=True)

@@ -151,6 +151,14 @@ int vplbm_get_mask(vplbm_sim s, uint8_t *body_id);
    ring (the last `ring` steps).  Synchronizes. */
 int vplbm_force_series(vplbm_sim s, int64_t first, int64_t count, double *out);
 
+/* Momentum exchange (the force evaluation of the paper's Section 3.3, after Ladd) on each body
+   for the current state: over every link between a fluid node x_f and a solid node x_s = x_f +
+   xi_a of body k, the momentum xi_a (g_a(x_f) + g_abar(x_s)) that the next streaming carries
+   into the body.  Links through periodic edges wrap, through other edges they do not exist.
+   fx, fy: host arrays of VPLBM_MAX_BODIES.  Its time mean equals that of the penalization force
+   in vplbm_obs (the body's own momentum changes average out).  Synchronizes. */
+int vplbm_momentum_exchange(vplbm_sim s, double *fx, double *fy);
+
 /* Number of steps done and the handle's stream (hipStream_t). */
 int vplbm_steps_done(vplbm_sim s, int64_t *steps);
 int vplbm_stream(vplbm_sim s, void **stream);

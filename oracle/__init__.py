@@ -80,6 +80,7 @@ def lib():
         L.orc_steps_done.restype = C.c_int64
         L.orc_get_obs.argtypes = [C.c_void_p, C.POINTER(Obs)]
         L.orc_get_fields.argtypes = [C.c_void_p, dp, dp, dp]
+        L.orc_momentum_exchange.argtypes = [C.c_void_p, dp, dp]
         _lib = L
     return _lib
 
@@ -266,6 +267,12 @@ class OracleSim:
         nb = o.nbodies
         return {"step": o.step, "mass": o.mass, "fx": np.array(o.fx[:nb]),
                 "fy": np.array(o.fy[:nb]), "fabs_sum": np.array(o.fabs_sum[:nb])}
+
+    def momentum_exchange(self):
+        """Per-body momentum-exchange force of the current state (fx, fy arrays)."""
+        fx, fy = _vec(MAX_BODIES), _vec(MAX_BODIES)
+        lib().orc_momentum_exchange(self.h, _dp(fx), _dp(fy))
+        return fx[:self.nbodies], fy[:self.nbodies]
 
     def fields(self):
         rho = np.zeros((self.ny, self.nx))

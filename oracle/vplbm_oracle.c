@@ -21,12 +21,16 @@
  *   R5 masks: node-centre inclusion; the lowest-index body containing a node owns it.
  *   R6 force on body k = -(sum over its nodes of the penalization force), i.e. the momentum the
  *      penalization removes from the fluid in that step.
- *   R7 convective outlet (the paper cites a convective condition whose source is not at hand):
+ *   R13 convective outlet (the paper cites a convective condition whose source is not at hand):
  *      the unknowns f_a, a in {3, 6, 7}, of the last column obey df/dt + U df/dx = 0 with U the
  *      inlet speed, discretised implicitly upwind:
  *        f_a(N-1, t+1) = (f_a(N-1, t) + U f_a(N-2, t+1)) / (1 + U),
  *      where f(N-2, t+1) is the streamed value of the neighbour column in the same step and
  *      f(N-1, t) the outlet value of the previous step (the current state's column at start).
+ *   R14 momentum exchange (the paper uses it for Section 3.3 but does not define it on a staircase):
+ *      over every link from a fluid node x_f to a solid node x_s = x_f + xi_a of body k,
+ *      F_k += xi_a (g_a(x_f) + g_abar(x_s)) on the stored post-collision state; links that leave
+ *      the domain through a non-periodic edge are skipped.
  */
 #include "vplbm_oracle.h"
 
@@ -560,4 +564,46 @@ void orc_get_fields(orc_sim *s, double *rho, double *ux, double *uy)
             if (ux) ux[i] = u[0];
             if (uy) uy[i] = u[1];
         }
+}
+
+/* Momentum exchange (the force evaluation the paper uses in Section 3.3, written for a penalized
+   body): streaming moves g_a(x_f) from a fluid node into the solid node x_s = x_f + xi_a and
+   g_abar(x_s) out of it, so the momentum the body region receives through that link in one step
+   is xi_a (g_a(x_f) + g_abar(x_s)); summed over every fluid-solid link of the body.  Links that
+   leave the lattice through a periodic edge wrap; through any other edge they do not exist. */
+void orc_momentum_exchange(const orc_sim *s, double fx[ORC_MAX_BODIES], double fy[ORC_MAX_BODIES])
+{
+    int nx = s->cfg.nx, ny = s->cfg.ny;
+    size_t N = (size_t)nx * ny;
+    int opp[9];
+    for (int a = 0; a < 9; a++)
+        for (int b = 0; b < 9; b++)
+            if (XI[b][0] == -XI[a][0] && XI[b][1] == -XI[a][1]) opp[a] = b;
+    nsum sx[ORC_MAX_BODIES], sy[ORC_MAX_BODIES];
+    memset(sx, 0, sizeof(sx));
+    memset(sy, 0, sizeof(sy));
+    for (int y = 0; y < ny; y++)
+        for (int x = 0; x < nx; x++) {
+            if (s->ids[(size_t)y * nx + x]) continue;             /* fluid node x_f */
+            for (int a = 1; a < 9; a++) {
+                int xs = x + XI[a][0], ys = y + XI[a][1];
+                if (xs < 0 || xs >= nx) {
+                    if (s->cfg.bc_xlo != ORC_PERIODIC) continue;
+                    xs = (xs + nx) % nx;
+                }
+                if (ys < 0 || ys >= ny) {
+                    if (s->cfg.bc_ylo != ORC_PERIODIC) continue;
+                    ys = (ys + ny) % ny;
+                }
+                int id = s->ids[(size_t)ys * nx + xs];
+                if (!id) continue;
+                double m = s->g[a * N + (size_t)y * nx + x] + s->g[opp[a] * N + (size_t)ys * nx + xs];
+                nadd(&sx[id - 1], XI[a][0] * m);
+                nadd(&sy[id - 1], XI[a][1] * m);
+            }
+        }
+    for (int k = 0; k < ORC_MAX_BODIES; k++) {
+        fx[k] = nval(sx[k]);
+        fy[k] = nval(sy[k]);
+    }
 }

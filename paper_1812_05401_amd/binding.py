@@ -77,6 +77,7 @@ SIGNATURES = [
     ("vplbm_set_populations", C.c_int, [C.c_void_p, _dp, C.c_int64]),
     ("vplbm_get_mask", C.c_int, [C.c_void_p, C.POINTER(C.c_uint8)]),
     ("vplbm_force_series", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, _dp]),
+    ("vplbm_momentum_exchange", C.c_int, [C.c_void_p, _dp, _dp]),
     ("vplbm_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("vplbm_stream", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     ("vplbm_bytes_per_update", C.c_int, [C.c_int32, C.POINTER(C.c_int64)]),
@@ -231,6 +232,12 @@ def vplbm_force_series(h, first, count):
     return out
 
 
+def vplbm_momentum_exchange(h, nbodies):
+    fx, fy = np.zeros(MAX_BODIES), np.zeros(MAX_BODIES)
+    check(load().vplbm_momentum_exchange(h, _ptr(fx), _ptr(fy)))
+    return fx[:nbodies], fy[:nbodies]
+
+
 def vplbm_steps_done(h):
     n = C.c_int64()
     check(load().vplbm_steps_done(h, C.byref(n)))
@@ -301,6 +308,9 @@ class Simulation:
 
     def mask(self):
         return vplbm_get_mask(self.h, self.shape)
+
+    def momentum_exchange(self):
+        return vplbm_momentum_exchange(self.h, self.nbodies)
 
     def force_series(self, first, count):
         return vplbm_force_series(self.h, first, count)

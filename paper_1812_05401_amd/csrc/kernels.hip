@@ -278,6 +278,59 @@ hipError_t launch_decode(int storage, const StepArgs &a, double *pop, hipStream_
     return hipGetLastError();
 }
 
+// Momentum exchange over the fluid-solid links of the current (post-collision) state: for a fluid
+// node x_f and a solid node x_s = x_f + xi_a of body k, streaming carries xi_a (g_a(x_f) +
+// g_abar(x_s)) into the body.  Links through a periodic edge wrap; through other edges they do
+// not exist.  out[2k], out[2k+1] accumulate body k's (fx, fy) in FP64.
+template <int S>
+__global__ __launch_bounds__(kBlock) void momentum_exchange_kernel(StepArgs a, double *out)
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    using E = typename C::elem;
+    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    __shared__ double acc[2 * kMaxBodies];
+    if (threadIdx.x < 2 * kMaxBodies) acc[threadIdx.x] = 0.0;
+    __syncthreads();
+    const int node = blockIdx.x * kBlock + threadIdx.x;
+    const Geom &g = a.g;
+    if (node < g.nx * g.ny) {
+        const int x = node % g.nx, y = node / g.nx;
+        const E *src = static_cast<const E *>(a.src);
+        if (a.mask[y * g.pitch + x] == 0) {
+#pragma unroll
+            for (int d = 1; d < 9; d++) {
+                int xs = x + cx[d], ys = y + cy[d];
+                if (xs < 0 || xs >= g.nx) {
+                    if (!g.xper) continue;
+                    xs += xs < 0 ? g.nx : -g.nx;
+                }
+                if (ys < 0 || ys >= g.ny) {
+                    if (!g.yper) continue;
+                    ys += ys < 0 ? g.ny : -g.ny;
+                }
+                const int id = a.mask[ys * g.pitch + xs];
+                if (!id) continue;
+                const double m = double(C::load(src + d * g.plane, y * g.pitch + x, weight<T>(d))) +
+                                 double(C::load(src + opp[d] * g.plane, ys * g.pitch + xs, weight<T>(opp[d])));
+                atomicAdd(&acc[2 * (id - 1)], cx[d] * m);
+                atomicAdd(&acc[2 * (id - 1) + 1], cy[d] * m);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kMaxBodies && acc[threadIdx.x] != 0.0) unsafeAtomicAdd(out + threadIdx.x, acc[threadIdx.x]);
+}
+
+hipError_t launch_momentum_exchange(int storage, const StepArgs &a, double *out, hipStream_t st)
+{
+    const dim3 grid = node_grid(a.g), block(kBlock);
+    VPLBM_DISPATCH(storage, momentum_exchange_kernel, a, out);
+    return hipGetLastError();
+}
+
 template <int S>
 __global__ void outlet_init_kernel(StepArgs a, void *prev)
 {

@@ -74,6 +74,8 @@ hipError_t launch_mask(uint8_t *mask, const Geom &g, const BodyParams *params,
                        hipStream_t st);
 
 hipError_t launch_advance(long long *t_base, long long n, hipStream_t st);
+// Momentum exchange of the state a.src: out[2k], out[2k+1] += body k's (fx, fy) (out zeroed).
+hipError_t launch_momentum_exchange(int storage, const StepArgs &a, double *out, hipStream_t st);
 // Convective outlet: prev = the last column's populations 3, 6, 7 of the state a.src.
 hipError_t launch_outlet_init(int storage, const StepArgs &a, void *prev, hipStream_t st);
 // Sum the sub-slots of step *t_base - 1 into its ring entry (without clearing them).

@@ -602,6 +602,23 @@ int vplbm_force_series(vplbm_sim s, int64_t first, int64_t count, double *out)
     return VPLBM_OK;
 }
 
+int vplbm_momentum_exchange(vplbm_sim s, double *fx, double *fy)
+{
+    if (!valid(s) || !fx || !fy) return fail(VPLBM_EINVAL, "invalid handle or NULL output");
+    int rc = ensure_staging(s, 2 * kMaxBodies * sizeof(double));
+    if (rc) return rc;
+    double out[2 * kMaxBodies];
+    HIP_TRY(launch_fill_f64(s->staging, 2 * kMaxBodies, 0.0, s->stream));
+    HIP_TRY(launch_momentum_exchange(s->storage, step_args(s, s->cur, 0), s->staging, s->stream));
+    HIP_TRY(hipMemcpyAsync(out, s->staging, sizeof out, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < kMaxBodies; k++) {
+        fx[k] = out[2 * k];
+        fy[k] = out[2 * k + 1];
+    }
+    return VPLBM_OK;
+}
+
 int vplbm_steps_done(vplbm_sim s, int64_t *steps)
 {
     if (!valid(s) || !steps) return fail(VPLBM_EINVAL, "invalid handle or NULL output");

@@ -1,0 +1,124 @@
+"""Parameter sweeps of Section 3 as a batched workload: many small simulations run together in
+the serving pool, each reduced to the relative L2 error of Eq. 20 against its analytic profile.
+
+* plane shear between penalized plates (Eq. 19): error against tau for SRT and against Lambda for
+  MRT (Fig. 3); the paper reports it practically vanishes at tau = 1/2 + sqrt(6)/4 (SRT) and at
+  Lambda = 3/8 (MRT, any tau);
+* Taylor-Couette flow between a rotating inner and a fixed outer cylinder (Eq. 21): error of the
+  vertical velocity against Lambda at tau = 0.7 and tau = 10 (Fig. 12; the paper runs tau = 10 at
+  Lambda = 0.0016), and against the grid resolution of Table 1 (Fig. 17).
+
+Readings: the shear flow is x-invariant, so the 200-node-long domain of the paper is run 64 nodes
+long (periodic); the plates are the rows y <= e and y >= e + H (reading R11 of the design notes).
+For Table 1 the radii scale with the box (R2 = 0.35 L, R1 = R2 - Ngrid), which reproduces the
+paper's R1 = 45, R2 = 70 at L = 200.
+"""
+import math
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+
+from . import analysis as A
+from . import inputs as I
+
+SHEAR_UD, SHEAR_E, SHEAR_H, SHEAR_NY = 0.01, 50.0, 100.0, 200
+
+
+def relax_steps(gap, tau, efolds=16.0, minimum=2000, maximum=600_000):
+    """Steps for the slowest viscous mode across a gap to decay by e^efolds: the diffusion time
+    gap^2 / (pi^2 nu) per e-fold with nu = (tau - 1/2)/3 (Eq. 6)."""
+    nu = (tau - 0.5) / 3.0
+    return int(min(maximum, max(minimum, efolds * gap * gap / (math.pi ** 2 * nu))))
+
+
+@dataclass
+class SweepPoint:
+    label: str
+    params: dict
+    case: I.Case
+    error_of: object      # callable(rho, ux, uy) -> float
+
+
+def shear_case(collision, tau, lam=0.375, steps=None, nx=64, storage="f64"):
+    ud, e, H, ny = SHEAR_UD, SHEAR_E, SHEAR_H, SHEAR_NY
+    steps = steps or relax_steps(H, tau)
+    bodies = [I.body("rect", (nx - 1) / 2, e / 2, hx=nx, hy=e / 2, ux=-ud),
+              I.body("rect", (nx - 1) / 2, (e + H + ny - 1) / 2, hx=nx, hy=(ny - 1 - e - H) / 2, ux=ud)]
+    case = I.Case(f"shear_{collision}_tau{tau:g}_lam{lam:g}", nx, ny, collision=collision,
+                  storage=storage, tau=tau, lam=lam, eta=1e-7, bc=I.ALL_PERIODIC, bodies=bodies,
+                  steps=steps)
+    y = np.arange(ny)
+    ua = (2 * ud / H) * (y - e) - ud                        # Eq. 19
+    fluid_rows = (y > e) & (y < e + H)
+
+    def err(rho, ux, uy):
+        fluid = np.broadcast_to(fluid_rows[:, None], ux.shape)
+        return A.l2_error(ux, np.broadcast_to(ua[:, None], ux.shape), fluid)
+    return SweepPoint(case.name, {"collision": collision, "tau": tau, "lambda": lam}, case, err)
+
+
+def couette_case(collision, tau, lam, L=200, ngrid=25, ud=0.01, steps=None, storage="f64"):
+    steps = steps or relax_steps(ngrid, tau)
+    R2 = 0.35 * L
+    R1 = R2 - ngrid
+    c = (L - 1) / 2
+    bodies = [I.body("disk", c, c, r=R1, omega=ud / R1), I.body("disk_outside", c, c, r=R2)]
+    case = I.Case(f"couette_{collision}_L{L}_tau{tau:g}_lam{lam:g}", L, L, collision=collision,
+                  storage=storage, tau=tau, lam=lam, eta=1e-7, bc=I.ALL_PERIODIC, bodies=bodies,
+                  steps=steps)
+    yy, xx = np.mgrid[0:L, 0:L]
+    dx, dy = xx - c, yy - c
+    r = np.hypot(dx, dy)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ut = -ud * R1 * r / (R2 ** 2 - R1 ** 2) + ud * R1 * R2 ** 2 / ((R2 ** 2 - R1 ** 2) * r)  # Eq. 21
+        vy = ut * dx / r
+    fluid = (r > R1) & (r < R2)
+
+    def err(rho, ux, uy):
+        return A.l2_error(uy, vy, fluid)
+    return SweepPoint(case.name, {"collision": collision, "tau": tau, "lambda": lam, "L": L,
+                                  "Ngrid": ngrid}, case, err)
+
+
+def fig3_shear():
+    pts = [shear_case("srt", t) for t in (0.6, 0.8, 1.0, 0.5 + math.sqrt(6) / 4, 1.3, 1.6, 2.0)]
+    for tau in (0.7, 1.5, 10.0):
+        pts += [shear_case("mrt", tau, lam) for lam in (0.1, 3 / 16, 0.3, 0.375, 0.5, 1.0)]
+    return pts
+
+
+def fig12_couette():
+    pts = [couette_case("mrt", 0.7, lam) for lam in (0.01, 0.05, 0.1, 3 / 16, 0.375, 0.75)]
+    pts += [couette_case("mrt", 10.0, lam) for lam in (0.0005, 0.0016, 0.005, 0.02, 0.06, 0.1, 0.2,
+                                                       0.375)]
+    pts += [couette_case("srt", t, 0.0) for t in (0.7, 1.0, 10.0)]
+    return pts
+
+
+def table1_grids():
+    """Couette at the resolutions of Table 1, MRT tau = 0.7, Lambda = 3/16 and 3/8."""
+    pts = []
+    for L, ng in ((200, 25), (400, 50), (600, 75), (800, 100), (800, 125)):
+        for lam in (3 / 16, 0.375):
+            pts.append(couette_case("mrt", 0.7, lam, L=L, ngrid=ng))
+    return pts
+
+
+def run(points: List[SweepPoint], budget_bytes=8 << 30, max_slots=256, steps_per_launch=256):
+    """Run every point through the pool at once; returns [(label, params, error, status)]."""
+    from . import binding as B
+    pool = B.Pool(budget_bytes, max_slots=max_slots, steps_per_launch=steps_per_launch)
+    ids = {pool.submit(p.case, p.case.steps, keep_fields=True): p for p in points}
+    out = {}
+    while len(out) < len(ids):
+        pool.advance()
+        for rid, p in ids.items():
+            if rid in out:
+                continue
+            st, _ = pool.status(rid)
+            if st in (B.DONE, B.FAILED):
+                obs, (rho, ux, uy) = pool.result(rid, fields=True)
+                out[rid] = (p.label, p.params, float(p.error_of(rho, ux, uy)), int(obs["status"]))
+    pool.close()
+    return [out[r] for r in ids]

@@ -208,3 +208,26 @@ def test_full_size_paper_cylinder_re500(gpu):
     g32.step(3)
     eg, er, eu, em, ef = compare(o, g32, 0, "paper_cylinder_f32")
     assert eg < 1e-5 and er < 1e-5 and eu < 1e-4 and em < 1e-6 and ef < 1e-4
+
+
+ME_CASES = [CASES[i] for i in (0, 2, 5, 13)]
+
+
+@pytest.mark.parametrize("spec", ME_CASES, ids=[c[0] for c in ME_CASES])
+def test_momentum_exchange_matches_oracle(gpu, spec):
+    """The link-based force over the post-collision state after 200 steps.  Scale: the summed
+    magnitude of the link terms, bounded by (number of fluid-solid links) x 2 max f."""
+    seed = zlib.crc32(spec[0].encode()) % 10000
+    case, ids = build_case(*spec, seed=seed)
+    o, g = make_pair(case, ids, seed)
+    o.step(200)
+    g.step(200)
+    ofx, ofy = o.momentum_exchange()
+    gfx, gfy = g.momentum_exchange()
+    solid = o.mask() != 0
+    links = sum(int(np.sum(~solid & np.roll(solid, (-ey, -ex), axis=(0, 1))))
+                for ex in (-1, 0, 1) for ey in (-1, 0, 1) if ex or ey)
+    sc = max(links, 1) * 2.0 * float(np.max(np.abs(o.populations())))
+    err = max(np.max(np.abs(gfx - ofx)), np.max(np.abs(gfy - ofy))) / sc
+    print(f"{spec[0]}: momentum exchange {ofx} {ofy}, rel {err:.2e}", flush=True)
+    assert err <= TOL64

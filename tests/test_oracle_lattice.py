@@ -284,3 +284,33 @@ def test_convective_outlet_advances_in_time_with_the_inlet_speed():
         g = z.pull_node(nx - 1, y)
         for a in (0, 1, 2, 4, 5, 8):
             assert f[a] == g[a]
+
+
+def _solid_momentum(s, ids, k):
+    """Momentum of the streamed (pre-collision) populations over the nodes of body k."""
+    xi, _ = xi_w()
+    p = np.zeros(2)
+    for y, x in zip(*np.nonzero(ids == k)):
+        p += xi.T @ s.pull_node(int(x), int(y))
+    return p
+
+
+@pytest.mark.parametrize("collision", [O.SRT, O.MRT])
+def test_momentum_exchange_balances_the_body_momentum(collision):
+    """Streaming is the only way momentum enters a body's nodes besides the penalization: the
+    link momentum exchange of the state stored by step t equals the change of the body's
+    momentum from step t to step t+1 plus the penalization force of step t:
+    F_ME(t) = P(t+1) - P(t) + F(t)."""
+    s, bodies = _random_sim(40, 30, 31, collision, nb=3)
+    ids = s.mask()
+    s.step(20)
+    nb = len(bodies)
+    p0 = [_solid_momentum(s, ids, k + 1) for k in range(nb)]
+    s.step(1)
+    o = s.obs()
+    fx, fy = s.momentum_exchange()      # on the state the step just stored
+    p1 = [_solid_momentum(s, ids, k + 1) for k in range(nb)]
+    for k in range(nb):
+        sc = o["fabs_sum"][k] + 1e-12
+        assert abs(fx[k] - (p1[k][0] - p0[k][0] + o["fx"][k])) < 1e-12 * sc + 1e-15
+        assert abs(fy[k] - (p1[k][1] - p0[k][1] + o["fy"][k])) < 1e-12 * sc + 1e-15
