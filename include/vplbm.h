@@ -49,10 +49,15 @@ enum vplbm_error {
    Lambda (Eq. 15); VPLBM_SRT is the single rate 1/tau with the Guo term (Eqs. 2, 7). */
 enum vplbm_collision { VPLBM_SRT = 0, VPLBM_MRT = 1 };
 
-/* Storage of the populations.  F64 and F32 store f.  F16S and BF16S store f - w_alpha (the
+/* Storage of the populations.  F64 stores f.  F32, F32D, F16S and BF16S store f - w_alpha (the
    lattice weights of Eq. 5, i.e. the deviation from the rest state at rho = 1) rounded to nearest
-   even in binary16 / bfloat16; the collision then runs in FP32.  F64 computes in FP64. */
-enum vplbm_storage { VPLBM_F64 = 0, VPLBM_F32 = 1, VPLBM_F16S = 2, VPLBM_BF16S = 3 };
+   even in binary32 / binary32 / binary16 / bfloat16.  Every format computes on f - w_alpha: F64
+   and F32D in FP64, F32, F16S and BF16S in FP32.  F32D moves F32's bytes; only its storage is
+   rounded to binary32, so long runs keep the mass and forces of an FP64 run, at some FP64
+   arithmetic cost.  get/set_populations convert to and from f in FP64; a get followed by a set
+   restores the stored bits, except that in F32 and F32D a stored |f - w_alpha| below about 2^-33
+   (where FP64's rounding of f reaches half its binary32 ulp) may come back changed by < 2^-56. */
+enum vplbm_storage { VPLBM_F64 = 0, VPLBM_F32 = 1, VPLBM_F16S = 2, VPLBM_BF16S = 3, VPLBM_F32D = 4 };
 
 /* Edge rules.  x edges: both PERIODIC, or VELOCITY (Zou-He inlet at x = 0 imposing (u_in_x,
    u_in_y)) with OUTFLOW (zero-gradient outlet at x = nx-1) or CONVECTIVE (the populations

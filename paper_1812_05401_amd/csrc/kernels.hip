@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
         int id = 0;
         if (active) {
             const Macro<T> m = update_node<S, NT>(src, dst, a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id);
-            const double rho_d = double(m.rho);
+            const double rho_d = 1.0 + double(m.drho);
             mass += rho_d;
             fx_d = double(m.fx);
             fy_d = double(m.fy);
@@ -143,6 +143,7 @@ hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st)
     case kF32: VPLBM_STEP(kF32); break;
     case kF16S: VPLBM_STEP(kF16S); break;
     case kBF16S: VPLBM_STEP(kBF16S); break;
+    case kF32D: VPLBM_STEP(kF32D); break;
     default: return hipErrorInvalidValue;
     }
 #undef VPLBM_STEP
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void readback_kernel(StepArgs a, double *rh
     T usx = T(0), usy = T(0);
     if (id) solid_velocity(a.bodies[id - 1], x, y, usx, usy);
     const Macro<T> m = moments(f, id != 0, usx, usy, T(a.p.k_relax), T(a.p.c_pen));
-    rho[node] = double(m.rho);
+    rho[node] = 1.0 + double(m.drho);
     ux[node] = double(m.ux);
     uy[node] = double(m.uy);
 }
@@ -186,20 +187,20 @@ __global__ __launch_bounds__(kBlock) void init_kernel(StepArgs a, const double *
     if (node >= a.g.nx * a.g.ny) return;
     const int x = node % a.g.nx, y = node / a.g.nx;
     const int i = y * a.g.pitch + x;
-    T rho, ux, uy;
+    T drho, ux, uy;
     if (rho_f) {
-        rho = T(rho_f[node]);
+        drho = T(rho_f[node] - 1.0);
         ux = T(ux_f[node]);
         uy = T(uy_f[node]);
     } else {
-        rho = T(rho0);
+        drho = T(rho0 - 1.0);
         ux = T(ux0);
         uy = T(uy0);
         const int id = a.mask[i];
         if (id) solid_velocity(a.bodies[id - 1], x, y, ux, uy);
     }
     T f[9];
-    equilibrium(rho, ux, uy, f);
+    equilibrium(drho, ux, uy, f);
     E *dst = static_cast<E *>(a.dst);
 #pragma unroll
     for (int k = 0; k < 9; k++) C::store(dst + k * a.g.plane, i, f[k], weight<T>(k));
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void encode_kernel(StepArgs a, const double
     const int i = y * a.g.pitch + x;
     E *dst = static_cast<E *>(a.dst);
 #pragma unroll
-    for (int k = 0; k < 9; k++) C::store(dst + k * a.g.plane, i, T(pop[(size_t)k * n + node]), weight<T>(k));
+    for (int k = 0; k < 9; k++) C::encode(dst + k * a.g.plane, i, pop[(size_t)k * n + node], weight<double>(k));
 }
 
 template <int S>
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void decode_kernel(StepArgs a, double *pop)
     const int i = y * a.g.pitch + x;
     const E *src = static_cast<const E *>(a.src);
 #pragma unroll
-    for (int k = 0; k < 9; k++) pop[(size_t)k * n + node] = double(C::load(src + k * a.g.plane, i, weight<T>(k)));
+    for (int k = 0; k < 9; k++) pop[(size_t)k * n + node] = C::decode(src + k * a.g.plane, i, weight<double>(k));
 }
 
 #define VPLBM_DISPATCH(storage, kern, ...)                                                        \
@@ -243,6 +244,7 @@ __global__ __launch_bounds__(kBlock) void decode_kernel(StepArgs a, double *pop)
     case kF32: kern<kF32><<<grid, block, 0, st>>>(__VA_ARGS__); break;                          \
     case kF16S: kern<kF16S><<<grid, block, 0, st>>>(__VA_ARGS__); break;                        \
     case kBF16S: kern<kBF16S><<<grid, block, 0, st>>>(__VA_ARGS__); break;                      \
+    case kF32D: kern<kF32D><<<grid, block, 0, st>>>(__VA_ARGS__); break;                        \
     default: return hipErrorInvalidValue;                                                        \
     }
 
@@ -286,7 +288,6 @@ template <int S>
 __global__ __launch_bounds__(kBlock) void momentum_exchange_kernel(StepArgs a, double *out)
 {
     using C = Codec<S>;
-    using T = typename C::real;
     using E = typename C::elem;
     constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -313,8 +314,8 @@ __global__ __launch_bounds__(kBlock) void momentum_exchange_kernel(StepArgs a, d
                 }
                 const int id = a.mask[ys * g.pitch + xs];
                 if (!id) continue;
-                const double m = double(C::load(src + d * g.plane, y * g.pitch + x, weight<T>(d))) +
-                                 double(C::load(src + opp[d] * g.plane, ys * g.pitch + xs, weight<T>(opp[d])));
+                const double m = C::decode(src + d * g.plane, y * g.pitch + x, weight<double>(d)) +
+                                 C::decode(src + opp[d] * g.plane, ys * g.pitch + xs, weight<double>(opp[d]));
                 atomicAdd(&acc[2 * (id - 1)], cx[d] * m);
                 atomicAdd(&acc[2 * (id - 1) + 1], cy[d] * m);
             }

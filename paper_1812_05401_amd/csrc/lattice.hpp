@@ -10,6 +10,14 @@
 // opposite pair relaxes with s+ = s_n, the antisymmetric half with s- = s_q, and the forcing term
 // splits as (1 - s+/2) F+ + (1 - s-/2) F-.  The SRT of Eqs. 2 and 7 is the case s+ = s- = 1/tau,
 // as the paper states for equal rates.  This form needs no 9x9 products.
+//
+// Shifted arithmetic.  Every kernel works on h_a = f_a - w_a, the deviation from the rest state
+// (rho = 1, u = 0), never on f itself: rho = 1 + sum h, j = sum xi h (sum xi w = 0), and the
+// collision, forcing, edge rules and Zou-He inlet are affine in f with w-preserving maps, so they
+// carry over to h with the equilibrium h^eq = w (drho + rho (3c + 4.5c^2 - 1.5u^2)).  In FP32 the
+// h are about 1e3 times smaller than f, and so are their rounding errors; rounding f ~ w every
+// step (which a uniform region repeats with the same sign) is what drifts the mass of long FP32
+// runs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,54 +25,70 @@
 
 namespace vplbm {
 
-enum Storage { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3 };
+enum Storage { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3, kF32D = 4 };
 
 // ---- storage codecs --------------------------------------------------------------------------
-// F16S/BF16S keep h = f - w_a, so the stored numbers are the small deviations from rest and the
-// format's relative precision applies to them rather than to f.
-
-template <int S> struct Codec;
-
+// load/store move h = f - w_a in the compute type `real`; encode/decode move f in FP64 (host
+// checkpoints, the momentum exchange).  F64 keeps f itself.  F32, F32D, F16S and BF16S keep h, so
+// the stored numbers are the small deviations from rest and the format's relative precision
+// applies to them rather than to f.  A decode/encode round trip gives back the stored bits: h + w
+// in FP64 is off by at most half an FP64 ulp of w (2^-57), below half an ulp of any h that binary16
+// or bfloat16 can hold and of any binary32 h above about 2^-33.  F32D computes in
+// FP64: with only the storage rounded to binary32, long runs keep FP64's mass and forces, and the
+// FP64 arithmetic costs this memory-bound step about a tenth of its time.
 // store_nt: the same value with a non-temporal store, for grids whose buffers do not fit in the
 // Infinity Cache (the next step's reads come from HBM anyway, so the writes need not be cached).
+template <int S> struct Codec;
+
 template <> struct Codec<kF64> {
     using elem = double;
     using real = double;
-    static __device__ __forceinline__ real load(const elem *p, int i, real) { return p[i]; }
-    static __device__ __forceinline__ void store(elem *p, int i, real v, real) { p[i] = v; }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real) { __builtin_nontemporal_store(v, p + i); }
+    static __device__ __forceinline__ real load(const elem *p, int i, real w) { return p[i] - w; }
+    static __device__ __forceinline__ void store(elem *p, int i, real h, real w) { p[i] = h + w; }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real w) { __builtin_nontemporal_store(h + w, p + i); }
+    static __device__ __forceinline__ double decode(const elem *p, int i, double) { return p[i]; }
+    static __device__ __forceinline__ void encode(elem *p, int i, double f, double) { p[i] = f; }
 };
 
-template <> struct Codec<kF32> {
+// binary32 h with FP32 (F32) or FP64 (F32D) arithmetic.
+template <typename R> struct CodecF32 {
     using elem = float;
-    using real = float;
+    using real = R;
     static __device__ __forceinline__ real load(const elem *p, int i, real) { return p[i]; }
-    static __device__ __forceinline__ void store(elem *p, int i, real v, real) { p[i] = v; }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real) { __builtin_nontemporal_store(v, p + i); }
+    static __device__ __forceinline__ void store(elem *p, int i, real h, real) { p[i] = float(h); }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real) { __builtin_nontemporal_store(float(h), p + i); }
+    static __device__ __forceinline__ double decode(const elem *p, int i, double w) { return double(p[i]) + w; }
+    static __device__ __forceinline__ void encode(elem *p, int i, double f, double w) { p[i] = float(f - w); }
 };
+template <> struct Codec<kF32> : CodecF32<float> {};
+template <> struct Codec<kF32D> : CodecF32<double> {};
 
 template <> struct Codec<kF16S> {
     using elem = _Float16;
     using real = float;
-    static __device__ __forceinline__ real load(const elem *p, int i, real w) { return (float)p[i] + w; }
-    static __device__ __forceinline__ void store(elem *p, int i, real v, real w) { p[i] = (_Float16)(v - w); }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real w)
+    static __device__ __forceinline__ real load(const elem *p, int i, real) { return (float)p[i]; }
+    static __device__ __forceinline__ void store(elem *p, int i, real h, real) { p[i] = (_Float16)h; }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real)
     {
-        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (_Float16)(v - w)),
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (_Float16)h),
                                     reinterpret_cast<unsigned short *>(p + i));
     }
+    static __device__ __forceinline__ double decode(const elem *p, int i, double w) { return double(p[i]) + w; }
+    static __device__ __forceinline__ void encode(elem *p, int i, double f, double w) { p[i] = (_Float16)(f - w); }
 };
 
 template <> struct Codec<kBF16S> {
     using elem = __bf16;
     using real = float;
-    static __device__ __forceinline__ real load(const elem *p, int i, real w) { return (float)p[i] + w; }
-    static __device__ __forceinline__ void store(elem *p, int i, real v, real w) { p[i] = (__bf16)(v - w); }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real v, real w)
+    static __device__ __forceinline__ real load(const elem *p, int i, real) { return (float)p[i]; }
+    static __device__ __forceinline__ void store(elem *p, int i, real h, real) { p[i] = (__bf16)h; }
+    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real)
     {
-        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (__bf16)(v - w)),
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (__bf16)h),
                                     reinterpret_cast<unsigned short *>(p + i));
     }
+    static __device__ __forceinline__ double decode(const elem *p, int i, double w) { return double(p[i]) + w; }
+    static __device__ __forceinline__ void encode(elem *p, int i, double f, double w) { p[i] = (__bf16)(float)(f - w); }
 };
 
 // Lattice weights of Eq. 5 in the compute type.
@@ -90,7 +114,8 @@ struct Geom {
 
 // Convective outlet on x = nx-1: the populations entering from x = nx (3, 6, 7) obey
 // df/dt + U df/dx = 0, implicitly upwind: f(nx-1, t+1) = (f(nx-1, t) + U f(nx-2, t+1)) / (1 + U).
-// prev holds f(nx-1, t) as [3][ny] in the compute type; the step writes next (the other parity).
+// The rule is affine with weights summing to one, so it holds for h as well.  prev holds
+// h(nx-1, t) as [3][ny] in the compute type; the step writes next (the other parity).
 struct Outlet {
     const void *prev;       // nullptr: zero-gradient outlet (or no outlet)
     void *next;             // nullptr: do not record (observation kernels)
@@ -120,7 +145,7 @@ __device__ __forceinline__ int edge_source(int a, int x, int y, const Geom &g, i
     return sy * g.pitch + sx;
 }
 
-// Pull the nine populations of node (x, y) from the post-collision planes `src`.
+// Pull the nine shifted populations h of node (x, y) from the post-collision planes `src`.
 template <int S>
 __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__ src, int x, int y,
                                      const Geom &g, const Outlet &o, typename Codec<S>::real f[9])
@@ -170,37 +195,42 @@ __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__
 
 // Zou-He velocity inlet on the west edge: the populations entering from x < 0 (1, 5, 8) are set
 // so that sum f = rho and sum xi f = rho (ux, uy), with rho from the known populations and the
-// non-equilibrium parts bounced back.
+// non-equilibrium parts bounced back.  On h: the known weights w0 + w2 + w4 + 2 (w3 + w6 + w7)
+// sum to 1, so rho - 1 = (H + ux) / (1 - ux) with H the same combination of h, and the unknowns
+// are set by the same formulas since opposite directions share a weight.
 template <typename T>
-__device__ __forceinline__ void zou_he_west(T f[9], T ux, T uy)
+__device__ __forceinline__ void zou_he_west(T h[9], T ux, T uy)
 {
-    T rho = (f[0] + f[2] + f[4] + T(2) * (f[3] + f[6] + f[7])) / (T(1) - ux);
-    T half_t = T(0.5) * (f[2] - f[4]);
+    T drho = (h[0] + h[2] + h[4] + T(2) * (h[3] + h[6] + h[7]) + ux) / (T(1) - ux);
+    T rho = T(1) + drho;
+    T half_t = T(0.5) * (h[2] - h[4]);
     T ru6 = rho * ux * T(1.0 / 6.0);
-    f[1] = f[3] + T(2.0 / 3.0) * rho * ux;
-    f[5] = f[7] - half_t + ru6 + T(0.5) * rho * uy;
-    f[8] = f[6] + half_t + ru6 - T(0.5) * rho * uy;
+    h[1] = h[3] + T(2.0 / 3.0) * rho * ux;
+    h[5] = h[7] - half_t + ru6 + T(0.5) * rho * uy;
+    h[8] = h[6] + half_t + ru6 - T(0.5) * rho * uy;
 }
 
 // ---- moments and penalization ------------------------------------------------------------------
 
 template <typename T> struct Macro {
-    T rho, ux, uy;   // density and penalized velocity (Eq. 18)
-    T fx, fy;        // penalization force (Eq. 17)
+    T drho, rho, ux, uy;   // density deviation rho - 1, density and penalized velocity (Eq. 18)
+    T fx, fy;              // penalization force (Eq. 17)
 };
 
-// Eqs. 8-9 and 17-18 with dt = 1.  In a solid node (chi = 1) the velocity and force are taken in
-// the algebraically equal forms u = u_s + (j/rho - u_s) k and f = -(j - rho u_s) c with
-// k = 1/(1 + 1/(2 eta)) and c = 1/(eta + 1/2): the literal forms subtract nearly equal numbers
-// (u - u_s is ~eta) and lose about -log10(eta) digits.
+// Eqs. 8-9 and 17-18 with dt = 1, from the shifted populations.  In a solid node (chi = 1) the
+// velocity and force are taken in the algebraically equal forms u = u_s + (j/rho - u_s) k and
+// f = -(j - rho u_s) c with k = 1/(1 + 1/(2 eta)) and c = 1/(eta + 1/2): the literal forms
+// subtract nearly equal numbers (u - u_s is ~eta) and lose about -log10(eta) digits.
 template <typename T>
-__device__ __forceinline__ Macro<T> moments(const T f[9], bool solid, T usx, T usy, T k_relax, T c_pen)
+__device__ __forceinline__ Macro<T> moments(const T h[9], bool solid, T usx, T usy, T k_relax, T c_pen)
 {
     Macro<T> m;
-    T rho = (f[0] + (f[1] + f[3])) + ((f[2] + f[4]) + ((f[5] + f[7]) + (f[6] + f[8])));
-    T jx = (f[1] - f[3]) + ((f[5] - f[7]) + (f[8] - f[6]));
-    T jy = (f[2] - f[4]) + ((f[5] - f[7]) + (f[6] - f[8]));
+    T drho = (h[0] + (h[1] + h[3])) + ((h[2] + h[4]) + ((h[5] + h[7]) + (h[6] + h[8])));
+    T jx = (h[1] - h[3]) + ((h[5] - h[7]) + (h[8] - h[6]));
+    T jy = (h[2] - h[4]) + ((h[5] - h[7]) + (h[6] - h[8]));
+    T rho = T(1) + drho;
     T inv_rho = T(1) / rho;
+    m.drho = drho;
     m.rho = rho;
     if (solid) {
         m.ux = usx + (jx * inv_rho - usx) * k_relax;
@@ -218,51 +248,53 @@ __device__ __forceinline__ Macro<T> moments(const T f[9], bool solid, T usx, T u
 
 // ---- collision -----------------------------------------------------------------------------------
 
-// One opposite pair (a, abar) with lattice weight w, c = xi_a . u and xf = xi_a . f.
+// One opposite pair (a, abar) of shifted populations with lattice weight w, c = xi_a . u and
+// xf = xi_a . f; q = -1.5 |u|^2.
 template <typename T>
-__device__ __forceinline__ void collide_pair(T &fa, T &fb, T c, T xf, T w, T rho, T base, T ufp,
-                                             T sp, T sm, T kp, T km)
+__device__ __forceinline__ void collide_pair(T &ha, T &hb, T c, T xf, T w, T drho, T rho, T q,
+                                             T ufp, T sp, T sm, T kp, T km)
 {
-    T feq_s = w * rho * (base + T(4.5) * c * c);      // symmetric part of Eq. 4
-    T feq_a = w * rho * (T(3) * c);                   // antisymmetric part of Eq. 4
-    T frc_s = w * (T(9) * c * xf - T(3) * ufp);       // symmetric part of Eq. 16
-    T frc_a = w * (T(3) * xf);                        // antisymmetric part of Eq. 16
-    T hs = T(0.5) * (fa + fb);
-    T ha = T(0.5) * (fa - fb);
-    T ns = hs - sp * (hs - feq_s) + kp * frc_s;
-    T na = ha - sm * (ha - feq_a) + km * frc_a;
-    fa = ns + na;
-    fb = ns - na;
+    T heq_s = w * (drho + rho * (q + T(4.5) * c * c));   // symmetric part of Eq. 4, minus w
+    T heq_a = w * rho * (T(3) * c);                      // antisymmetric part of Eq. 4
+    T frc_s = w * (T(9) * c * xf - T(3) * ufp);          // symmetric part of Eq. 16
+    T frc_a = w * (T(3) * xf);                           // antisymmetric part of Eq. 16
+    T hs = T(0.5) * (ha + hb);
+    T hd = T(0.5) * (ha - hb);
+    T ns = hs - sp * (hs - heq_s) + kp * frc_s;
+    T na = hd - sm * (hd - heq_a) + km * frc_a;
+    ha = ns + na;
+    hb = ns - na;
 }
 
 // Two-rate collision with the split forcing term: sp/sm are the even/odd rates, kp = 1 - sp/2,
-// km = 1 - sm/2.  In place on f.
+// km = 1 - sm/2.  In place on the shifted populations h.
 template <typename T>
-__device__ __forceinline__ void collide(T f[9], const Macro<T> &m, T sp, T sm, T kp, T km)
+__device__ __forceinline__ void collide(T h[9], const Macro<T> &m, T sp, T sm, T kp, T km)
 {
-    const T ux = m.ux, uy = m.uy, rho = m.rho;
-    const T base = T(1) - T(1.5) * (ux * ux + uy * uy);
+    const T ux = m.ux, uy = m.uy, rho = m.rho, drho = m.drho;
+    const T q = T(-1.5) * (ux * ux + uy * uy);
     const T ufp = ux * m.fx + uy * m.fy;
     {
-        T feq0 = W<T>::rest * rho * base;
+        T heq0 = W<T>::rest * (drho + rho * q);
         T frc0 = W<T>::rest * (T(-3) * ufp);
-        f[0] = f[0] - sp * (f[0] - feq0) + kp * frc0;
+        h[0] = h[0] - sp * (h[0] - heq0) + kp * frc0;
     }
-    collide_pair(f[1], f[3], ux, m.fx, W<T>::axis, rho, base, ufp, sp, sm, kp, km);
-    collide_pair(f[2], f[4], uy, m.fy, W<T>::axis, rho, base, ufp, sp, sm, kp, km);
-    collide_pair(f[5], f[7], ux + uy, m.fx + m.fy, W<T>::diag, rho, base, ufp, sp, sm, kp, km);
-    collide_pair(f[6], f[8], uy - ux, m.fy - m.fx, W<T>::diag, rho, base, ufp, sp, sm, kp, km);
+    collide_pair(h[1], h[3], ux, m.fx, W<T>::axis, drho, rho, q, ufp, sp, sm, kp, km);
+    collide_pair(h[2], h[4], uy, m.fy, W<T>::axis, drho, rho, q, ufp, sp, sm, kp, km);
+    collide_pair(h[5], h[7], ux + uy, m.fx + m.fy, W<T>::diag, drho, rho, q, ufp, sp, sm, kp, km);
+    collide_pair(h[6], h[8], uy - ux, m.fy - m.fx, W<T>::diag, drho, rho, q, ufp, sp, sm, kp, km);
 }
 
-// Equilibrium of Eq. 4 (used to initialise).
+// Equilibrium of Eq. 4 minus the weights (used to initialise); drho = rho - 1.
 template <typename T>
-__device__ __forceinline__ void equilibrium(T rho, T ux, T uy, T f[9])
+__device__ __forceinline__ void equilibrium(T drho, T ux, T uy, T h[9])
 {
-    const T base = T(1) - T(1.5) * (ux * ux + uy * uy);
+    const T rho = T(1) + drho;
+    const T q = T(-1.5) * (ux * ux + uy * uy);
     const T c[9] = {T(0), ux, uy, -ux, -uy, ux + uy, uy - ux, -ux - uy, ux - uy};
 #pragma unroll
     for (int a = 0; a < 9; a++)
-        f[a] = weight<T>(a) * rho * (base + T(3) * c[a] + T(4.5) * c[a] * c[a]);
+        h[a] = weight<T>(a) * (drho + rho * (q + T(3) * c[a] + T(4.5) * c[a] * c[a]));
 }
 
 // ---- obstacles ------------------------------------------------------------------------------------
@@ -301,7 +333,7 @@ update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::
 {
     using C = Codec<S>;
     using T = typename C::real;
-    T f[9];
+    T f[9];                  // shifted populations h = f - w
     pull<S>(src, x, y, g, o, f);
     if (g.inlet && x == 0) zou_he_west(f, T(p.uin_x), T(p.uin_y));
     const int i = y * g.pitch + x;

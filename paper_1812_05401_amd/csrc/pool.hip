@@ -65,7 +65,7 @@ __device__ __forceinline__ double pool_node(const PoolSim &d, int parity, int x,
     const auto m = update_node<S>(src, dst, d.mask, d.bodies, d.g, none, d.p, x, y, id);
     fx = double(m.fx);
     fy = double(m.fy);
-    return double(m.rho);
+    return 1.0 + double(m.drho);
 }
 
 // One lattice step of every resident simulation: workgroup w (< *ntiles) updates one tile.
@@ -92,6 +92,7 @@ __global__ __launch_bounds__(kBlock) void pool_step_kernel(PoolSim *sims, const 
         case kF64: rho = pool_node<kF64>(d, parity, x, y, fx, fy, id); break;
         case kF32: rho = pool_node<kF32>(d, parity, x, y, fx, fy, id); break;
         case kF16S: rho = pool_node<kF16S>(d, parity, x, y, fx, fy, id); break;
+        case kF32D: rho = pool_node<kF32D>(d, parity, x, y, fx, fy, id); break;
         default: rho = pool_node<kBF16S>(d, parity, x, y, fx, fy, id); break;
         }
     }

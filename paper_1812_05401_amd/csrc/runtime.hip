@@ -40,11 +40,16 @@ int fail(int code, const char *fmt, ...)
 
 
 
+static_assert(kF64 == VPLBM_F64 && kF32 == VPLBM_F32 && kF16S == VPLBM_F16S &&
+                  kBF16S == VPLBM_BF16S && kF32D == VPLBM_F32D,
+              "device storage ids follow the ABI");
+
 int elem_bytes(int storage)
 {
     switch (storage) {
     case VPLBM_F64: return 8;
-    case VPLBM_F32: return 4;
+    case VPLBM_F32:
+    case VPLBM_F32D: return 4;
     case VPLBM_F16S:
     case VPLBM_BF16S: return 2;
     default: return 0;

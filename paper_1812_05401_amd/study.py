@@ -59,7 +59,7 @@ def run_series(case, steps, storage=None, snapshots=(), chunk=4000, stream=None,
             "momentum_exchange": np.array(me).reshape(-1, 3)}
 
 
-def compare_storages(case, steps, storages=("f64", "f32", "f16s", "bf16s"), snapshots=(1000, 10000),
+def compare_storages(case, steps, storages=("f64", "f32", "f32d", "f16s", "bf16s"), snapshots=(1000, 10000),
                      stats_from=None, stream=None, log=None, dump=None, me_every=0):
     """Run `case` in every storage format and compare each with the FP64 run (and with FP32).
     `dump`: optional .npz path for the raw per-step series."""

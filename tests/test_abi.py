@@ -36,6 +36,7 @@ def test_binding_covers_the_header():
 def test_bytes_per_update():
     assert B.vplbm_bytes_per_update("f64") == 145
     assert B.vplbm_bytes_per_update("f32") == 73
+    assert B.vplbm_bytes_per_update("f32d") == 73
     assert B.vplbm_bytes_per_update("f16s") == 37
     assert B.vplbm_bytes_per_update("bf16s") == 37
     with pytest.raises(B.VplbmError):
