@@ -183,9 +183,14 @@ def main():
                          "cylinder_wake_8192x2048) in every storage format for --steps steps and "
                          "print the comparison against FP64")
     ap.add_argument("--dump", default="", help="with --precision-study: .npz for the series")
-    ap.add_argument("--sweep", default="", choices=["", "fig3", "fig12", "table1"],
+    ap.add_argument("--sweep", default="", choices=["", "fig3", "fig12", "table1", "fig5", "fig14"],
                     help="instead of the benchmark: run one of the paper's parameter sweeps "
-                         "through the serving pool and print the L2 errors")
+                         "through the serving pool and print the L2 errors (fig5, fig14: steps "
+                         "to convergence under the early stop)")
+    ap.add_argument("--stop", type=float, default=0.0,
+                    help="with --sweep: retire each point early once its convergence residual "
+                         "over --stop-every steps is below this tolerance")
+    ap.add_argument("--stop-every", type=int, default=1000)
     ap.add_argument("--me-every", type=int, default=0,
                     help="with --precision-study: sample the momentum-exchange force every N steps")
     ap.add_argument("--storages", default="f64,f32,f32d,f16s,bf16s",
@@ -214,15 +219,16 @@ def main():
     if args.sweep:
         from paper_1812_05401_amd import sweeps
         pts = {"fig3": sweeps.fig3_shear, "fig12": sweeps.fig12_couette,
-               "table1": sweeps.table1_grids}[args.sweep]()
+               "table1": sweeps.table1_grids, "fig5": sweeps.fig5_convergence,
+               "fig14": sweeps.fig14_convergence}[args.sweep]()
+        stop = (args.stop, args.stop_every) if args.stop > 0 else sweeps.CONVERGENCE_STOP.get(args.sweep)
         t0 = time.perf_counter()
-        res = sweeps.run(pts)
+        res = sweeps.run(pts, stop=stop)
         wall = time.perf_counter() - t0
-        lups = sum(p.case.nodes * p.case.steps for p in pts)
-        print(json.dumps({"sweep": args.sweep, "points": len(pts), "lattice_updates": lups,
-                          "wall_s": wall, "mlups": lups / wall / 1e6,
-                          "results": [{"label": l, **prm, "l2_error": e, "status": st}
-                                      for l, prm, e, st in res]}), flush=True)
+        lups = sum(p.case.nodes * r["steps"] for p, r in zip(pts, res))
+        print(json.dumps({"sweep": args.sweep, "points": len(pts), "stop": stop,
+                          "lattice_updates": lups, "wall_s": wall, "mlups": lups / wall / 1e6,
+                          "results": res}), flush=True)
         return
     if args.precision_study:
         from paper_1812_05401_amd import study

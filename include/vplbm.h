@@ -148,6 +148,15 @@ int vplbm_init_fields(vplbm_sim s, const double *rho, const double *ux, const do
 int vplbm_get_populations(vplbm_sim s, double *pop);
 int vplbm_set_populations(vplbm_sim s, const double *pop, int64_t step);
 
+/* Convergence residual (the relative L2 norm of Eq. 20 applied to the change of the velocity
+   field): residual = sqrt(sum |u - u_prev|^2 / sum |u|^2) over the fluid nodes of the current
+   state, where u_prev is the velocity at the previous call.  The first call stores the field and
+   returns +inf; a zero field returns 0.  u is the velocity field vplbm_observables returns (the
+   penalized velocity the next step would take).  The sums run in FP64 in a fixed order, so the
+   value does not depend on scheduling.  The first call allocates 16 bytes per node for the
+   snapshot.  Synchronizes. */
+int vplbm_residual(vplbm_sim s, double *residual);
+
 /* Copy the current body-id plane (host nx*ny).  Synchronizes. */
 int vplbm_get_mask(vplbm_sim s, uint8_t *body_id);
 
@@ -175,7 +184,7 @@ int vplbm_bytes_per_update(int32_t storage, int64_t *bytes);
 /* ---- serving pool -----------------------------------------------------------------------
  * Many independent simulations resident on one GPU at once, advanced together: every call to
  * vplbm_pool_advance replays one captured HIP graph of `steps_per_launch` launches of a
- * persistent batched step kernel that walks a device table of tiles spanning all resident
+ * batched step kernel with one workgroup per tile of a device table spanning all resident
  * simulations (each simulation's per-node arithmetic is the single-simulation step's), then
  * retires the finished ones and admits queued requests, first come first served, while the
  * memory budget and the slots allow.  A simulation's results do not depend on what else is
@@ -209,6 +218,18 @@ int vplbm_pool_create(const vplbm_pool_config *cfg, vplbm_pool *out);
    config or moving bodies.  *id receives the request id (>= 0). */
 int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *bodies,
                       int32_t nbodies, int64_t nsteps, int32_t keep_fields, int64_t *id);
+
+/* Early stop for a steady run (a QUEUED request): every `every` >= 1 steps (checked at the end of
+   each launch, so at multiples of steps_per_launch at the earliest) the pool computes the
+   request's convergence residual on the device, as vplbm_residual defines it with u_prev the
+   field of the previous check, and once it is below `tol` > 0 the request runs one more step
+   (whose mass and forces are reduced) and finishes.  It costs 16 bytes per node more, charged
+   against the budget (VPLBM_EBUDGET if the request no longer fits it). */
+int vplbm_pool_set_stop(vplbm_pool p, int64_t id, double tol, int64_t every);
+
+/* The last residual the pool computed for a request with an early stop (+inf before the second
+   check); valid until vplbm_pool_result releases the request. */
+int vplbm_pool_residual(vplbm_pool p, int64_t id, double *residual);
 
 /* Wait for the previous launch, retire finished simulations, admit queued ones, and launch the
    next chunk of steps (asynchronous).  Any output pointer may be NULL. */

@@ -81,6 +81,8 @@ def lib():
         L.orc_get_obs.argtypes = [C.c_void_p, C.POINTER(Obs)]
         L.orc_get_fields.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_momentum_exchange.argtypes = [C.c_void_p, dp, dp]
+        L.orc_residual.argtypes = [C.c_void_p, dp, dp]
+        L.orc_residual.restype = C.c_double
         _lib = L
     return _lib
 
@@ -273,6 +275,13 @@ class OracleSim:
         fx, fy = _vec(MAX_BODIES), _vec(MAX_BODIES)
         lib().orc_momentum_exchange(self.h, _dp(fx), _dp(fy))
         return fx[:self.nbodies], fy[:self.nbodies]
+
+    def residual(self, ux_prev, uy_prev):
+        """Relative L2 change of the fluid velocity against a previous field (Eq. 20 form)."""
+        a = np.ascontiguousarray(ux_prev, dtype=np.float64)
+        b = np.ascontiguousarray(uy_prev, dtype=np.float64)
+        assert a.shape == b.shape == (self.ny, self.nx)
+        return lib().orc_residual(self.h, _dp(a), _dp(b))
 
     def fields(self):
         rho = np.zeros((self.ny, self.nx))

@@ -566,6 +566,30 @@ void orc_get_fields(orc_sim *s, double *rho, double *ux, double *uy)
         }
 }
 
+/* Convergence residual: the relative L2 norm of Eq. 20 with the previous velocity field in the
+   place of the exact one, sqrt(sum |u - u_prev|^2 / sum |u|^2) over the fluid nodes, u being the
+   fields of the current state (orc_get_fields).  A zero field gives 0, or +inf if u_prev is not
+   zero there. */
+double orc_residual(orc_sim *s, const double *ux_prev, const double *uy_prev)
+{
+    size_t n = (size_t)s->cfg.nx * s->cfg.ny;
+    double *ux = malloc(n * sizeof(double)), *uy = malloc(n * sizeof(double));
+    orc_get_fields(s, NULL, ux, uy);
+    nsum d2 = {0, 0}, u2 = {0, 0};
+    for (size_t i = 0; i < n; i++) {
+        if (s->ids[i]) continue;
+        double dx = ux[i] - ux_prev[i], dy = uy[i] - uy_prev[i];
+        nadd(&d2, dx * dx);
+        nadd(&d2, dy * dy);
+        nadd(&u2, ux[i] * ux[i]);
+        nadd(&u2, uy[i] * uy[i]);
+    }
+    free(ux);
+    free(uy);
+    if (nval(u2) > 0) return sqrt(nval(d2) / nval(u2));
+    return nval(d2) > 0 ? INFINITY : 0.0;
+}
+
 /* Momentum exchange (the force evaluation the paper uses in Section 3.3, written for a penalized
    body): streaming moves g_a(x_f) from a fluid node into the solid node x_s = x_f + xi_a and
    g_abar(x_s) out of it, so the momentum the body region receives through that link in one step

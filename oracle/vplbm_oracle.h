@@ -93,6 +93,9 @@ void orc_step(orc_sim *s, int64_t nsteps);
 int64_t orc_steps_done(const orc_sim *s);
 void orc_get_obs(const orc_sim *s, orc_obs *out);
 void orc_get_fields(orc_sim *s, double *rho, double *ux, double *uy);
+/* sqrt(sum |u - u_prev|^2 / sum |u|^2) over the fluid nodes of the current fields (Eq. 20 with the
+   previous field as the reference): the convergence residual. */
+double orc_residual(orc_sim *s, const double *ux_prev, const double *uy_prev);
 /* Momentum exchange on body k over the links between fluid and solid nodes of the current
    (post-collision) state: the momentum the next streaming carries into the body. */
 void orc_momentum_exchange(const orc_sim *s, double fx[ORC_MAX_BODIES], double fy[ORC_MAX_BODIES]);

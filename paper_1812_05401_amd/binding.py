@@ -78,12 +78,15 @@ SIGNATURES = [
     ("vplbm_get_mask", C.c_int, [C.c_void_p, C.POINTER(C.c_uint8)]),
     ("vplbm_force_series", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, _dp]),
     ("vplbm_momentum_exchange", C.c_int, [C.c_void_p, _dp, _dp]),
+    ("vplbm_residual", C.c_int, [C.c_void_p, _dp]),
     ("vplbm_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("vplbm_stream", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     ("vplbm_bytes_per_update", C.c_int, [C.c_int32, C.POINTER(C.c_int64)]),
     ("vplbm_pool_create", C.c_int, [C.POINTER(PoolConfig), C.POINTER(C.c_void_p)]),
     ("vplbm_pool_submit", C.c_int, [C.c_void_p, C.POINTER(Config), C.POINTER(Body), C.c_int32,
                                      C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
+    ("vplbm_pool_set_stop", C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_int64]),
+    ("vplbm_pool_residual", C.c_int, [C.c_void_p, C.c_int64, _dp]),
     ("vplbm_pool_advance", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32)]),
     ("vplbm_pool_status", C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
@@ -238,6 +241,12 @@ def vplbm_momentum_exchange(h, nbodies):
     return fx[:nbodies], fy[:nbodies]
 
 
+def vplbm_residual(h):
+    r = C.c_double()
+    check(load().vplbm_residual(h, C.byref(r)))
+    return r.value
+
+
 def vplbm_steps_done(h):
     n = C.c_int64()
     check(load().vplbm_steps_done(h, C.byref(n)))
@@ -312,6 +321,10 @@ class Simulation:
     def momentum_exchange(self):
         return vplbm_momentum_exchange(self.h, self.nbodies)
 
+    def residual(self):
+        """Relative L2 change of the fluid velocity since the previous call (+inf at the first)."""
+        return vplbm_residual(self.h)
+
     def force_series(self, first, count):
         return vplbm_force_series(self.h, first, count)
 
@@ -374,7 +387,9 @@ class Pool:
         self.h = h.value
         self.shapes = {}
 
-    def submit(self, case, nsteps=None, keep_fields=False):
+    def submit(self, case, nsteps=None, keep_fields=False, stop=None):
+        """Queue `case` for `nsteps` steps; stop = (tol, every) retires it early once its
+        convergence residual over `every` steps is below tol."""
         bodies = case.bodies
         arr = (Body * max(1, len(bodies)))(*[make_body(b) for b in bodies])
         rid = C.c_int64()
@@ -382,7 +397,14 @@ class Pool:
                                        int(nsteps if nsteps is not None else case.steps),
                                        1 if keep_fields else 0, C.byref(rid)))
         self.shapes[rid.value] = (case.ny, case.nx)
+        if stop is not None:
+            check(load().vplbm_pool_set_stop(self.h, rid.value, float(stop[0]), int(stop[1])))
         return rid.value
+
+    def residual(self, rid):
+        r = C.c_double()
+        check(load().vplbm_pool_residual(self.h, int(rid), C.byref(r)))
+        return r.value
 
     def advance(self):
         r, q, f = C.c_int32(), C.c_int32(), C.c_int32()

@@ -157,22 +157,70 @@ __global__ __launch_bounds__(kBlock) void readback_kernel(StepArgs a, double *rh
                                                            double *uy)
 {
     using C = Codec<S>;
-    using T = typename C::real;
     using E = typename C::elem;
     const int node = blockIdx.x * kBlock + threadIdx.x;
     if (node >= a.g.nx * a.g.ny) return;
     const int x = node % a.g.nx, y = node / a.g.nx;
-    T f[9];
-    const Outlet o{a.outlet.prev, nullptr, a.outlet.u};   // observe only: do not record
-    pull<S>(static_cast<const E *>(a.src), x, y, a.g, o, f);
-    if (a.g.inlet && x == 0) zou_he_west(f, T(a.p.uin_x), T(a.p.uin_y));
-    const int id = a.mask[y * a.g.pitch + x];
-    T usx = T(0), usy = T(0);
-    if (id) solid_velocity(a.bodies[id - 1], x, y, usx, usy);
-    const Macro<T> m = moments(f, id != 0, usx, usy, T(a.p.k_relax), T(a.p.c_pen));
+    int id;
+    const auto m = observe_node<S>(static_cast<const E *>(a.src), a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id);
     rho[node] = 1.0 + double(m.drho);
     ux[node] = double(m.ux);
     uy[node] = double(m.uy);
+}
+
+// Convergence residual, node part: at every fluid node, |u - u_snap|^2 and |u|^2 of the velocity
+// the next step would take; the snapshot becomes u at every node.  Per-workgroup sums (waves in
+// order) go to part[blockIdx.x][2], so the result does not depend on scheduling.
+template <int S>
+__global__ __launch_bounds__(kBlock) void residual_kernel(StepArgs a, double *snap, double *part)
+{
+    using C = Codec<S>;
+    using E = typename C::elem;
+    __shared__ double wsum[kBlock / 64][2];
+    const int n = a.g.nx * a.g.ny;
+    const int node = blockIdx.x * kBlock + threadIdx.x;
+    double d2 = 0.0, u2 = 0.0;
+    if (node < n) {
+        const int x = node % a.g.nx, y = node / a.g.nx;
+        int id;
+        const auto m = observe_node<S>(static_cast<const E *>(a.src), a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id);
+        const double ux = double(m.ux), uy = double(m.uy);
+        if (id == 0) {
+            const double dx = ux - snap[node], dy = uy - snap[n + node];
+            d2 = dx * dx + dy * dy;
+            u2 = ux * ux + uy * uy;
+        }
+        snap[node] = ux;
+        snap[n + node] = uy;
+    }
+    d2 = wave_sum(d2);
+    u2 = wave_sum(u2);
+    if ((threadIdx.x & 63) == 0) {
+        wsum[threadIdx.x >> 6][0] = d2;
+        wsum[threadIdx.x >> 6][1] = u2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; w++) v += wsum[w][threadIdx.x];
+        part[2 * blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+// Sum part[nparts][2] in a fixed order into out[2] (one wave: lane l takes parts l, l + 64, ...).
+__global__ void residual_fold_kernel(const double *part, int nparts, double *out)
+{
+    double d2 = 0.0, u2 = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 64) {
+        d2 += part[2 * i];
+        u2 += part[2 * i + 1];
+    }
+    d2 = wave_sum(d2);
+    u2 = wave_sum(u2);
+    if (threadIdx.x == 0) {
+        out[0] = d2;
+        out[1] = u2;
+    }
 }
 
 template <int S>
@@ -255,6 +303,17 @@ hipError_t launch_readback(int storage, const StepArgs &a, double *rho, double *
 {
     const dim3 grid = node_grid(a.g), block(kBlock);
     VPLBM_DISPATCH(storage, readback_kernel, a, rho, ux, uy);
+    return hipGetLastError();
+}
+
+int residual_parts(const Geom &g) { return (g.nx * g.ny + kBlock - 1) / kBlock; }
+
+hipError_t launch_residual(int storage, const StepArgs &a, double *snap, double *part, double *out,
+                           hipStream_t st)
+{
+    const dim3 grid = node_grid(a.g), block(kBlock);
+    VPLBM_DISPATCH(storage, residual_kernel, a, snap, part);
+    residual_fold_kernel<<<1, 64, 0, st>>>(part, (int)grid.x, out);
     return hipGetLastError();
 }
 

@@ -74,6 +74,12 @@ hipError_t launch_mask(uint8_t *mask, const Geom &g, const BodyParams *params,
                        hipStream_t st);
 
 hipError_t launch_advance(long long *t_base, long long n, hipStream_t st);
+// Convergence residual of the state a.src against the velocity snapshot snap ([2][ny*nx] FP64):
+// out[0] = sum over fluid nodes of |u - u_snap|^2, out[1] = sum of |u|^2 (fixed summation
+// order); the snapshot becomes u.  part holds residual_parts(g) x 2 doubles.
+int residual_parts(const Geom &g);
+hipError_t launch_residual(int storage, const StepArgs &a, double *snap, double *part, double *out,
+                           hipStream_t st);
 // Momentum exchange of the state a.src: out[2k], out[2k+1] += body k's (fx, fy) (out zeroed).
 hipError_t launch_momentum_exchange(int storage, const StepArgs &a, double *out, hipStream_t st);
 // Convective outlet: prev = the last column's populations 3, 6, 7 of the state a.src.

@@ -350,6 +350,26 @@ update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::
     return m;
 }
 
+// The moments the next step would take at node (x, y) of the state `src`, without storing
+// anything: pull, edges (the convective outlet is read, not recorded), body velocity, Eqs. 8-9 and
+// 17-18.  Density is 1 + drho and velocity (ux, uy) in the compute type; id is the body id.
+template <int S>
+__device__ __forceinline__ Macro<typename Codec<S>::real>
+observe_node(const typename Codec<S>::elem *__restrict__ src, const uint8_t *__restrict__ mask,
+             const BodyState *__restrict__ bodies, const Geom &g, const Outlet &o,
+             const NodeParams &p, int x, int y, int &id)
+{
+    using T = typename Codec<S>::real;
+    T f[9];
+    const Outlet ro{o.prev, nullptr, o.u};
+    pull<S>(src, x, y, g, ro, f);
+    if (g.inlet && x == 0) zou_he_west(f, T(p.uin_x), T(p.uin_y));
+    id = mask[y * g.pitch + x];
+    T usx = T(0), usy = T(0);
+    if (id) solid_velocity(bodies[id - 1], x, y, usx, usy);
+    return moments(f, id != 0, usx, usy, T(p.k_relax), T(p.c_pen));
+}
+
 // ---- wave reductions ------------------------------------------------------------------------------
 
 __device__ __forceinline__ double wave_sum(double v)

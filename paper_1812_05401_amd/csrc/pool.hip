@@ -47,6 +47,12 @@ struct PoolSim {
     long long t0, target;    // pool step at admission; steps to run
     unsigned status;
     double obs[kRingWidth];  // folded final observables
+    // early stop (tol > 0): residual checks at done >= next_check, every `every` steps
+    double tol, residual;
+    long long every, next_check;
+    int have_snap;
+    double *snap;            // [2][ny*nx] velocity at the last check
+    double *rpart;           // [ntiles][2] residual partial sums
 };
 
 struct TileRef {
@@ -136,6 +142,98 @@ __global__ void pool_fold_kernel(PoolSim *sims, int slot)
     }
 }
 
+// Whether a simulation checks its residual after this launch (the same test in both kernels).
+__device__ __forceinline__ bool residual_due(const PoolSim &d, long long done)
+{
+    return d.active && d.tol > 0.0 && done >= d.next_check && done < d.target;
+}
+
+// Residual check, node part, on the state after the launch's steps: |u - u_snap|^2 and |u|^2 at
+// a fluid node; the snapshot becomes u.
+template <int S>
+__device__ __forceinline__ void pool_residual_node(const PoolSim &d, int parity, int x, int y,
+                                                   double &d2, double &u2)
+{
+    using E = typename Codec<S>::elem;
+    const Outlet none{nullptr, nullptr, 0.0};
+    int id;
+    const auto m = observe_node<S>(static_cast<const E *>(d.buf[parity]), d.mask, d.bodies, d.g, none, d.p, x, y, id);
+    const size_t n = (size_t)d.g.nx * d.g.ny, i = (size_t)y * d.g.nx + x;
+    const double ux = double(m.ux), uy = double(m.uy);
+    if (id == 0) {
+        const double dx = ux - d.snap[i], dy = uy - d.snap[n + i];
+        d2 = dx * dx + dy * dy;
+        u2 = ux * ux + uy * uy;
+    }
+    d.snap[i] = ux;
+    d.snap[n + i] = uy;
+}
+
+// One workgroup per tile, as the step kernel; per-tile sums (waves in a fixed order).
+__global__ __launch_bounds__(kBlock) void pool_residual_kernel(PoolSim *sims, const TileRef *tiles,
+                                                               const int *ntiles,
+                                                               const long long *t_base, int t_off)
+{
+    __shared__ double part[kBlock / 64][2];
+    const int n = *ntiles;
+    if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const TileRef tr = tiles[xcd_tile(blockIdx.x, n)];
+    const PoolSim &d = sims[tr.slot];
+    const long long done = *t_base + t_off - d.t0;
+    if (!residual_due(d, done)) return;                       // uniform over the workgroup
+    const int x = (tr.tile % d.ntx) * kPoolTileW + lane;
+    const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
+    double d2 = 0.0, u2 = 0.0;
+    if (x < d.g.nx && y < d.g.ny) {
+        const int parity = (int)(done & 1);
+        switch (d.storage) {
+        case kF64: pool_residual_node<kF64>(d, parity, x, y, d2, u2); break;
+        case kF32: pool_residual_node<kF32>(d, parity, x, y, d2, u2); break;
+        case kF16S: pool_residual_node<kF16S>(d, parity, x, y, d2, u2); break;
+        case kF32D: pool_residual_node<kF32D>(d, parity, x, y, d2, u2); break;
+        default: pool_residual_node<kBF16S>(d, parity, x, y, d2, u2); break;
+        }
+    }
+    d2 = wave_sum(d2);
+    u2 = wave_sum(u2);
+    if (lane == 0) {
+        part[wave][0] = d2;
+        part[wave][1] = u2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock / 64; w++) v += part[w][threadIdx.x];
+        d.rpart[2 * tr.tile + threadIdx.x] = v;
+    }
+}
+
+// Residual check, decision: workgroup s (one wave) folds slot s's tile sums in a fixed order;
+// below the tolerance the simulation gets one more step, whose observables the step kernel
+// reduces.
+__global__ void pool_residual_fold_kernel(PoolSim *sims, const long long *t_base, int t_off)
+{
+    PoolSim &d = sims[blockIdx.x];
+    const long long done = *t_base + t_off - d.t0;
+    if (!residual_due(d, done)) return;                       // uniform over the workgroup
+    double d2 = 0.0, u2 = 0.0;
+    for (int t = threadIdx.x; t < d.ntiles; t += 64) {
+        d2 += d.rpart[2 * t];
+        u2 += d.rpart[2 * t + 1];
+    }
+    d2 = wave_sum(d2);
+    u2 = wave_sum(u2);
+    if (threadIdx.x == 0) {
+        double r = u2 > 0.0 ? sqrt(d2 / u2) : (d2 > 0.0 ? INFINITY : 0.0);
+        if (!d.have_snap) r = INFINITY;
+        d.residual = r;
+        d.have_snap = 1;
+        d.next_check = done + d.every;
+        if (r < d.tol) d.target = done + 1;
+    }
+}
+
 __global__ void pool_advance_kernel(long long *t, long long n) { *t += n; }
 
 }  // namespace vplbm
@@ -148,6 +246,9 @@ struct Request {
     std::vector<vplbm_body> bodies;
     int64_t nsteps = 0;
     int keep_fields = 0;
+    double tol = 0.0;
+    int64_t every = 0;
+    double residual = INFINITY;
     int state = VPLBM_QUEUED;
     int slot = -1;
     uint64_t bytes = 0;
@@ -160,6 +261,8 @@ struct Request {
     BodyParams *params = nullptr;
     BodyState *state_dev = nullptr;
     double *partials = nullptr;
+    double *snap = nullptr;
+    double *rpart = nullptr;
 };
 
 int pool_geometry(const vplbm_config &c, Geom &g, int &ntx, int &ntiles)
@@ -176,14 +279,15 @@ int pool_geometry(const vplbm_config &c, Geom &g, int &ntx, int &ntiles)
     return VPLBM_OK;
 }
 
-uint64_t bytes_needed(const vplbm_config &c)
+uint64_t bytes_needed(const vplbm_config &c, bool stop = false)
 {
     Geom g;
     int ntx, ntiles;
     pool_geometry(c, g, ntx, ntiles);
     const uint64_t pop = (uint64_t)9 * g.plane * elem_bytes(c.storage);
+    const uint64_t residual = stop ? 2 * (uint64_t)g.nx * g.ny * sizeof(double) + (uint64_t)ntiles * 2 * sizeof(double) : 0;
     return 2 * pop + (uint64_t)g.pitch * g.ny + sizeof(BodyParams) * kMaxBodies +
-           sizeof(BodyState) * kMaxBodies + (uint64_t)ntiles * kRingWidth * sizeof(double);
+           sizeof(BodyState) * kMaxBodies + (uint64_t)ntiles * kRingWidth * sizeof(double) + residual;
 }
 
 std::mutex g_pool_mu;
@@ -198,6 +302,7 @@ struct vplbm_pool_s {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
     int grid_cap = 0;                     // workgroups per step launch in the captured graph
+    bool graph_checks = false;            // the graph ends with the residual-check kernels
     PoolSim *d_sims = nullptr;
     TileRef *d_tiles = nullptr;
     int *d_ntiles = nullptr;
@@ -229,9 +334,11 @@ bool pool_valid(const void *p)
 
 void free_request_memory(vplbm_pool p, Request &r)
 {
-    void *ptrs[] = {r.buf[0], r.buf[1], r.mask, r.params, r.state_dev, r.partials};
+    void *ptrs[] = {r.buf[0], r.buf[1], r.mask, r.params, r.state_dev, r.partials, r.snap, r.rpart};
     for (void *q : ptrs)
         if (q) (void)hipFreeAsync(q, p->stream);
+    r.snap = nullptr;
+    r.rpart = nullptr;
     r.buf[0] = r.buf[1] = nullptr;
     r.mask = nullptr;
     r.params = nullptr;
@@ -267,6 +374,7 @@ int retire(vplbm_pool p, int slot)
     PoolSim &d = p->h_sims[slot];
     const long long done = steps_done(p, d);
     r.done = done;
+    r.residual = d.residual;
     memset(&r.obs, 0, sizeof r.obs);
     r.obs.step = done - 1;
     r.obs.nbodies = (int32_t)r.bodies.size();
@@ -327,8 +435,11 @@ int admit(vplbm_pool p, Request &r, int slot)
         {(void **)&r.params, sizeof(BodyParams) * kMaxBodies},
         {(void **)&r.state_dev, sizeof(BodyState) * kMaxBodies},
         {(void **)&r.partials, (size_t)d.ntiles * kRingWidth * sizeof(double)},
+        {(void **)&r.snap, r.tol > 0.0 ? 2 * (size_t)d.g.nx * d.g.ny * sizeof(double) : 0},
+        {(void **)&r.rpart, r.tol > 0.0 ? (size_t)d.ntiles * 2 * sizeof(double) : 0},
     };
     for (auto &a : allocs) {
+        if (a.n == 0) continue;
         if (hipMallocAsync(a.ptr, a.n, p->stream) != hipSuccess) {
             (void)hipGetLastError();
             free_request_memory(p, r);
@@ -356,6 +467,12 @@ int admit(vplbm_pool p, Request &r, int slot)
     d.active = 1;
     d.t0 = p->t_host;
     d.target = r.nsteps;
+    d.tol = r.tol;
+    d.every = r.every;
+    d.next_check = r.every;
+    d.residual = INFINITY;
+    d.snap = r.snap;
+    d.rpart = r.rpart;
     StepArgs a{};
     a.dst = d.buf[0];
     a.mask = d.mask;
@@ -374,7 +491,10 @@ int admit(vplbm_pool p, Request &r, int slot)
 
 int ensure_pool_graph(vplbm_pool p)
 {
-    if (p->graph && p->grid_cap >= p->ntiles && p->grid_cap <= 8 * (p->ntiles > 4096 ? p->ntiles : 4096))
+    bool checks = false;
+    for (const PoolSim &d : p->h_sims) checks |= d.active && d.tol > 0.0;
+    if (p->graph && p->grid_cap >= p->ntiles && p->grid_cap <= 8 * (p->ntiles > 4096 ? p->ntiles : 4096) &&
+        p->graph_checks == checks)
         return VPLBM_OK;
     if (p->graph) {
         HIP_TRY(hipGraphExecDestroy(p->graph));
@@ -391,10 +511,20 @@ int ensure_pool_graph(vplbm_pool p)
         pool_step_kernel<<<dim3(cap), dim3(kBlock), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j);
         e = hipGetLastError();
     }
+    if (e == hipSuccess && checks) {
+        const int n = p->cfg.steps_per_launch;
+        pool_residual_kernel<<<dim3(cap), dim3(kBlock), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, n);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+            pool_residual_fold_kernel<<<dim3(p->cfg.max_slots), dim3(64), 0, p->cap_stream>>>(p->d_sims, p->d_t, n);
+            e = hipGetLastError();
+        }
+    }
     if (e == hipSuccess) {
         pool_advance_kernel<<<1, 1, 0, p->cap_stream>>>(p->d_t, p->cfg.steps_per_launch);
         e = hipGetLastError();
     }
+    p->graph_checks = checks;
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
     if (e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -532,6 +662,36 @@ int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *b
     p->reqs[r.id] = r;
     p->queue.push_back(r.id);
     *id = r.id;
+    return VPLBM_OK;
+}
+
+int vplbm_pool_set_stop(vplbm_pool p, int64_t id, double tol, int64_t every)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    auto it = p->reqs.find(id);
+    if (it == p->reqs.end()) return fail(VPLBM_EINVAL, "unknown request %lld", (long long)id);
+    Request &r = it->second;
+    if (r.state != VPLBM_QUEUED) return fail(VPLBM_ESTATE, "request %lld is no longer queued", (long long)id);
+    if (!(tol > 0.0) || !isfinite(tol)) return fail(VPLBM_EINVAL, "tol must be finite and > 0");
+    if (every < 1) return fail(VPLBM_EINVAL, "every must be >= 1");
+    const uint64_t need = bytes_needed(r.cfg, true);
+    if (need > p->cfg.budget_bytes)
+        return fail(VPLBM_EBUDGET, "simulation with a residual snapshot needs %llu bytes, pool budget is %llu",
+                    (unsigned long long)need, (unsigned long long)p->cfg.budget_bytes);
+    r.tol = tol;
+    r.every = every;
+    r.bytes = need;
+    return VPLBM_OK;
+}
+
+int vplbm_pool_residual(vplbm_pool p, int64_t id, double *residual)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    if (!residual) return fail(VPLBM_EINVAL, "residual is NULL");
+    auto it = p->reqs.find(id);
+    if (it == p->reqs.end()) return fail(VPLBM_EINVAL, "unknown request %lld", (long long)id);
+    const Request &r = it->second;
+    *residual = r.state == VPLBM_RUNNING ? p->h_sims[r.slot].residual : r.residual;
     return VPLBM_OK;
 }
 

@@ -103,6 +103,9 @@ struct vplbm_sim_s {
     bool unstable = false;
     NodeParams params{};
     int nt_store = 0;
+    double *snap = nullptr;              // convergence residual: [2][ny*nx] velocity snapshot,
+    double *rpart = nullptr;             // then per-workgroup partials and the two sums
+    bool have_snap = false;
 };
 
 namespace {
@@ -226,7 +229,7 @@ void release(vplbm_sim s)
     for (int p = 0; p < 2; p++)
         if (s->graph[p]) (void)hipGraphExecDestroy(s->graph[p]);
     void *ptrs[] = {s->buf[0], s->buf[1], s->mask, s->d_params, s->d_state, s->ring, s->acc,
-                    s->status, s->t_dev, s->staging, s->outlet[0], s->outlet[1]};
+                    s->status, s->t_dev, s->staging, s->outlet[0], s->outlet[1], s->snap, s->rpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -621,6 +624,34 @@ int vplbm_momentum_exchange(vplbm_sim s, double *fx, double *fy)
         fx[k] = out[2 * k];
         fy[k] = out[2 * k + 1];
     }
+    return VPLBM_OK;
+}
+
+int vplbm_residual(vplbm_sim s, double *residual)
+{
+    if (!valid(s) || !residual) return fail(VPLBM_EINVAL, "invalid handle or NULL output");
+    const size_t n = (size_t)s->g.nx * s->g.ny;
+    const int parts = residual_parts(s->g);
+    if (!s->snap) {
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (hipMalloc(&s->snap, 2 * n * sizeof(double)) != hipSuccess ||
+            hipMalloc(&s->rpart, (2 * (size_t)parts + 2) * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            if (s->snap) (void)hipFree(s->snap);
+            s->snap = nullptr;
+            return fail(VPLBM_ENOMEM, "cannot allocate the residual snapshot (%zu bytes)", 2 * n * sizeof(double));
+        }
+        s->have_snap = false;
+    }
+    double sums[2];
+    if (s->moving) HIP_TRY(place_bodies(s, 0, s->stream));   // the fields' time, as the readback
+    HIP_TRY(launch_residual(s->storage, step_args(s, s->cur, 0), s->snap, s->rpart, s->rpart + 2 * parts, s->stream));
+    HIP_TRY(hipMemcpyAsync(sums, s->rpart + 2 * parts, sizeof sums, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (!s->have_snap) *residual = INFINITY;
+    else if (sums[1] > 0.0) *residual = sqrt(sums[0] / sums[1]);
+    else *residual = sums[0] > 0.0 ? INFINITY : 0.0;
+    s->have_snap = true;
     return VPLBM_OK;
 }
 

@@ -105,20 +105,49 @@ def table1_grids():
     return pts
 
 
-def run(points: List[SweepPoint], budget_bytes=8 << 30, max_slots=256, steps_per_launch=256):
-    """Run every point through the pool at once; returns [(label, params, error, status)]."""
+def fig5_convergence(max_steps=600_000):
+    """Iterations to convergence of the plane shear (Figs 5-7): each point runs until its
+    residual over 1000 steps is below 1e-12 (the pool's early stop) or max_steps.  The paper finds
+    SRT tau = 1/2 + sqrt(6)/4 and MRT Lambda = 3/8 at that tau the fastest to an error near zero."""
+    opt = 0.5 + math.sqrt(6) / 4
+    pts = [shear_case("srt", t, steps=max_steps) for t in (0.6, 0.8, 1.0, opt, 1.3, 1.6, 2.0)]
+    pts += [shear_case("mrt", t, 0.375, steps=max_steps) for t in (0.7, opt, 1.5, 10.0)]
+    return pts
+
+
+def fig14_convergence(max_steps=200_000):
+    """Iterations to convergence of the Taylor-Couette flow (Figs 14-15), residual over 1000
+    steps below 1e-5: MRT at tau = 0.7 (Lambda = 0.1, 3/16) and tau = 10 (Lambda = 0.0016, the
+    paper's choice, and 0.06), SRT at tau = 0.7, 1 and 10."""
+    pts = [couette_case("mrt", 0.7, lam, steps=max_steps) for lam in (0.1, 3 / 16)]
+    pts += [couette_case("mrt", 10.0, lam, steps=max_steps) for lam in (0.0016, 0.06)]
+    pts += [couette_case("srt", t, 0.0, steps=max_steps) for t in (0.7, 1.0, 10.0)]
+    return pts
+
+
+CONVERGENCE_STOP = {"fig5": (1e-12, 1000), "fig14": (1e-5, 1000)}
+
+
+def run(points: List[SweepPoint], budget_bytes=8 << 30, max_slots=256, steps_per_launch=256,
+        stop=None):
+    """Run every point through the pool at once, for its step count or, with stop = (tol,
+    every), until its convergence residual over `every` steps falls below tol.  Returns one
+    record per point: label, parameters, L2 error, status, steps run and last residual."""
     from . import binding as B
     pool = B.Pool(budget_bytes, max_slots=max_slots, steps_per_launch=steps_per_launch)
-    ids = {pool.submit(p.case, p.case.steps, keep_fields=True): p for p in points}
+    ids = {pool.submit(p.case, p.case.steps, keep_fields=True, stop=stop): p for p in points}
     out = {}
     while len(out) < len(ids):
         pool.advance()
         for rid, p in ids.items():
             if rid in out:
                 continue
-            st, _ = pool.status(rid)
+            st, done = pool.status(rid)
             if st in (B.DONE, B.FAILED):
+                res = pool.residual(rid)
                 obs, (rho, ux, uy) = pool.result(rid, fields=True)
-                out[rid] = (p.label, p.params, float(p.error_of(rho, ux, uy)), int(obs["status"]))
+                out[rid] = {"label": p.label, **p.params, "l2_error": float(p.error_of(rho, ux, uy)),
+                            "status": int(obs["status"]), "steps": int(done),
+                            "residual": None if math.isinf(res) else float(res)}
     pool.close()
     return [out[r] for r in ids]

@@ -95,4 +95,11 @@ def test_null_and_foreign_handles_are_rejected():
     assert lib.vplbm_stream(bogus, C.byref(s)) == B.EINVAL
     assert lib.vplbm_get_populations(bogus, None) == B.EINVAL
     assert lib.vplbm_force_series(bogus, 0, 1, None) == B.EINVAL
+    r = C.c_double()
+    assert lib.vplbm_residual(bogus, C.byref(r)) == B.EINVAL
+    assert lib.vplbm_momentum_exchange(bogus, None, None) == B.EINVAL
     assert "invalid handle" in B.last_error()
+    assert lib.vplbm_pool_set_stop(bogus, 0, 1e-6, 10) == B.EINVAL
+    assert lib.vplbm_pool_residual(bogus, 0, C.byref(r)) == B.EINVAL
+    assert lib.vplbm_pool_advance(None, None, None, None) == B.EINVAL
+    assert "invalid pool" in B.last_error()

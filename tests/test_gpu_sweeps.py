@@ -14,7 +14,7 @@ def test_shear_optimum_through_the_pool(gpu):
     pts = [S.shear_case("srt", 0.5 + math.sqrt(6) / 4), S.shear_case("srt", 0.8),
            S.shear_case("mrt", 1.5, 0.375), S.shear_case("mrt", 10.0, 0.375),
            S.shear_case("mrt", 1.5, 3 / 16)]
-    res = {lbl: (err, st) for lbl, _, err, st in S.run(pts)}
+    res = {r["label"]: (r["l2_error"], r["status"]) for r in S.run(pts)}
     errs = [res[p.label][0] for p in pts]
     assert all(res[p.label][1] == 0 for p in pts)
     assert errs[0] < 1e-6 and errs[2] < 1e-6 and errs[3] < 1e-6

@@ -5,7 +5,9 @@
   close to zero at SRT tau = 1/2 + sqrt(6)/4 and at MRT Lambda = 3/8 (Section 3.1);
 * Taylor-Couette flow between a rotating disk and a fixed annulus: Eq. 21 and the L2 error of
   Eq. 20, which stays finite because the curved walls are staircases (Section 3.2);
-* SRT at tau = 10 gives unrealistic Couette results while MRT does not (Section 3.2, Fig. 10).
+* SRT at tau = 10 gives unrealistic Couette results while MRT does not (Section 3.2, Fig. 10);
+* the convergence residual (Eq. 20 against the field N steps earlier) of a decaying shear wave is
+  exp(nu k^2 N) - 1, and it counts fluid nodes only.
 """
 import math
 
@@ -42,6 +44,39 @@ def test_shear_wave_decays_at_the_lattice_viscosity(collision, tau, lam):
     rate = math.log(a1 / a2) / 600
     nu = (tau - 0.5) / 3.0
     assert abs(rate / (nu * (2 * np.pi / ny) ** 2) - 1.0) < 0.01
+
+
+def test_residual_of_a_decaying_shear_wave():
+    """The field N steps earlier is the current one times exp(nu k^2 N), so the relative change
+    measured against the current field is exp(nu k^2 N) - 1."""
+    nx, ny, A, tau, N = 4, 64, 1e-3, 0.8, 200
+    mode = np.sin(2 * np.pi * np.arange(ny) / ny)
+    s = O.OracleSim(nx, ny, O.SRT, tau=tau)
+    ones = np.ones((ny, nx))
+    s.init_fields(ones, A * mode[:, None] * ones, 0 * ones)
+    s.step(100)
+    _, ux0, uy0 = s.fields()
+    s.step(N)
+    nu, k = (tau - 0.5) / 3.0, 2 * np.pi / ny
+    expect = math.exp(nu * k * k * N) - 1.0
+    assert abs(s.residual(ux0, uy0) / expect - 1.0) < 0.01
+    assert s.residual(*s.fields()[1:]) == 0.0
+
+
+def test_residual_ignores_solid_nodes():
+    s = O.OracleSim(40, 30, O.MRT, tau=0.7, lam=3 / 16)
+    s.set_bodies([O.make_body(O.RECT, cx=20, cy=15, hx=5, hy=4)])
+    s.init_uniform(1.0, 0.005, 0.03)
+    s.step(30)
+    _, ux, uy = s.fields()
+    solid = s.mask() != 0
+    fluid = ~solid
+    assert solid.sum() > 0
+    px, py = ux.copy(), 0.5 * uy               # only the y component changed, by half
+    px[solid], py[solid] = 1e3, -1e3           # whatever the solid nodes hold does not count
+    share = np.sum(uy[fluid] ** 2) / np.sum(ux[fluid] ** 2 + uy[fluid] ** 2)
+    assert 0.9 < share < 0.99
+    assert abs(s.residual(px, py) - 0.5 * math.sqrt(share)) < 1e-14
 
 
 def _plane_shear(collision, tau, lam, steps, eta=1e-7, nx=4, ny=200):
