@@ -219,6 +219,14 @@ int vplbm_pool_create(const vplbm_pool_config *cfg, vplbm_pool *out);
 int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *bodies,
                       int32_t nbodies, int64_t nsteps, int32_t keep_fields, int64_t *id);
 
+/* Admission cap on the lattice nodes of the resident simulations (0, the default: none).  A
+   queued request is admitted only while the resident nodes plus its own stay within the cap, or
+   when nothing is resident.  Resident simulations advance in lock step, one step per launch each,
+   so every resident node slows every other simulation down: a cap near what fills the GPU keeps
+   small requests batched while long ones do not crowd each other, which shortens the tail of
+   time-to-result at high load.  Takes effect at the next vplbm_pool_advance. */
+int vplbm_pool_set_admission(vplbm_pool p, uint64_t max_resident_nodes);
+
 /* Early stop for a steady run (a QUEUED request): every `every` >= 1 steps (checked at the end of
    each launch, so at multiples of steps_per_launch at the earliest) the pool computes the
    request's convergence residual on the device, as vplbm_residual defines it with u_prev the

@@ -86,6 +86,7 @@ SIGNATURES = [
     ("vplbm_pool_submit", C.c_int, [C.c_void_p, C.POINTER(Config), C.POINTER(Body), C.c_int32,
                                      C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
     ("vplbm_pool_set_stop", C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_int64]),
+    ("vplbm_pool_set_admission", C.c_int, [C.c_void_p, C.c_uint64]),
     ("vplbm_pool_residual", C.c_int, [C.c_void_p, C.c_int64, _dp]),
     ("vplbm_pool_advance", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32)]),
@@ -400,6 +401,10 @@ class Pool:
         if stop is not None:
             check(load().vplbm_pool_set_stop(self.h, rid.value, float(stop[0]), int(stop[1])))
         return rid.value
+
+    def set_admission(self, max_resident_nodes):
+        """Cap on the resident lattice nodes (0: none)."""
+        check(load().vplbm_pool_set_admission(self.h, int(max_resident_nodes)))
 
     def residual(self, rid):
         r = C.c_double()

@@ -12,17 +12,19 @@ namespace vplbm {
 
 // ---- the fused step --------------------------------------------------------------------------
 
-// Sum sub-slots [kSub][kRingWidth] of step t into ring entry t (fixed order: deterministic).
-__device__ __forceinline__ void fold_step(const StepArgs &a, long long t, bool clear)
+// Sum value q of the sub-slots [kSub][kRingWidth] of step t into ring entry t, with one wave:
+// lane l adds sub-slots l, l + 64, ... in order, then a fixed butterfly adds the lanes, so the
+// result does not depend on which workgroup folds or when.  One memory round trip, not kSub.
+__device__ __forceinline__ void fold_value(const StepArgs &a, long long t, int q, bool clear)
 {
     double *acc = a.acc + (size_t)(t & 1) * kSub * kRingWidth;
-    for (int q = threadIdx.x; q < kRingWidth; q += blockDim.x) {
-        double v = 0.0;
-        for (int b = 0; b < kSub; b++) v += acc[b * kRingWidth + q];
-        a.ring[(size_t)(t % a.ring_len) * kRingWidth + q] = v;
-        if (clear)
-            for (int b = 0; b < kSub; b++) acc[b * kRingWidth + q] = 0.0;
-    }
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+    for (int b = lane; b < kSub; b += 64) v += acc[b * kRingWidth + q];
+    v = wave_sum(v);
+    if (lane == 0) a.ring[(size_t)(t % a.ring_len) * kRingWidth + q] = v;
+    if (clear)
+        for (int b = lane; b < kSub; b += 64) acc[b * kRingWidth + q] = 0.0;
 }
 
 // Body forces of one row of nodes: only waves holding solid nodes do any work, one pass per
@@ -55,7 +57,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
     if (a.reduce) {
         if (threadIdx.x < kRingWidth) lds_acc[threadIdx.x] = 0.0;
         // The previous step's partials are complete (kernel boundary): fold and clear them.
-        if (blockIdx.x == 0 && t >= 1) fold_step(a, t - 1, true);
+        // Workgroup q's first wave folds value q (all of them if the grid is smaller).
+        if (t >= 1 && threadIdx.x < 64)
+            for (int q = blockIdx.x; q < kRingWidth; q += gridDim.x) fold_value(a, t - 1, q, true);
         __syncthreads();
     }
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -96,7 +100,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 __global__ void fold_kernel(StepArgs a)
 {
     const long long t = *a.t_base;
-    if (t >= 1) fold_step(a, t - 1, false);
+    if (t >= 1)
+        for (int q = 0; q < kRingWidth; q++) fold_value(a, t - 1, q, false);
 }
 
 hipError_t launch_fold(const StepArgs &a, hipStream_t st)

@@ -321,6 +321,8 @@ struct vplbm_pool_s {
     uint64_t used = 0;
     bool in_flight = false;
     int32_t finished = 0;
+    uint64_t max_nodes = 0;               // admission cap on resident lattice nodes (0: none)
+    uint64_t resident_nodes = 0;
 };
 
 namespace {
@@ -415,6 +417,7 @@ int retire(vplbm_pool p, int slot)
     r.state = r.obs.status ? VPLBM_FAILED : VPLBM_DONE;
     free_request_memory(p, r);
     p->used -= r.bytes;
+    p->resident_nodes -= (uint64_t)r.cfg.nx * r.cfg.ny;
     r.slot = -1;
     p->slot_req[slot] = -1;
     memset(&p->h_sims[slot], 0, sizeof(PoolSim));
@@ -427,6 +430,8 @@ int retire(vplbm_pool p, int slot)
 int admit(vplbm_pool p, Request &r, int slot)
 {
     if (p->used + r.bytes > p->cfg.budget_bytes) return 0;
+    const uint64_t nodes = (uint64_t)r.cfg.nx * r.cfg.ny;
+    if (p->max_nodes && p->resident_nodes > 0 && p->resident_nodes + nodes > p->max_nodes) return 0;
     PoolSim d{};
     pool_geometry(r.cfg, d.g, d.ntx, d.ntiles);
     const size_t pop = (size_t)9 * d.g.plane * elem_bytes(r.cfg.storage);
@@ -486,6 +491,7 @@ int admit(vplbm_pool p, Request &r, int slot)
     r.slot = slot;
     r.state = VPLBM_RUNNING;
     p->used += r.bytes;
+    p->resident_nodes += nodes;
     return 1;
 }
 
@@ -681,6 +687,13 @@ int vplbm_pool_set_stop(vplbm_pool p, int64_t id, double tol, int64_t every)
     r.tol = tol;
     r.every = every;
     r.bytes = need;
+    return VPLBM_OK;
+}
+
+int vplbm_pool_set_admission(vplbm_pool p, uint64_t max_resident_nodes)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    p->max_nodes = max_resident_nodes;
     return VPLBM_OK;
 }
 

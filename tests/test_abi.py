@@ -101,5 +101,6 @@ def test_null_and_foreign_handles_are_rejected():
     assert "invalid handle" in B.last_error()
     assert lib.vplbm_pool_set_stop(bogus, 0, 1e-6, 10) == B.EINVAL
     assert lib.vplbm_pool_residual(bogus, 0, C.byref(r)) == B.EINVAL
+    assert lib.vplbm_pool_set_admission(bogus, 1000) == B.EINVAL
     assert lib.vplbm_pool_advance(None, None, None, None) == B.EINVAL
     assert "invalid pool" in B.last_error()

@@ -26,8 +26,10 @@ def small_requests(seed=7, n=6, storage="f64"):
     return out
 
 
-def run(pool_cls, cases, budget, slots=64, spl=32):
+def run(pool_cls, cases, budget, slots=64, spl=32, max_nodes=0):
     pool = pool_cls(budget, max_slots=slots, steps_per_launch=spl)
+    if max_nodes:
+        pool.set_admission(max_nodes)
     ids = [pool.submit(c, c.steps, keep_fields=True) for c in cases]
     res, max_running = {}, 0
     while len(res) < len(ids):
@@ -59,6 +61,25 @@ def test_alone_and_in_the_mix_are_bitwise_equal(gpu):
         assert np.array_equal(oa["fx"], om["fx"]) and np.array_equal(oa["fy"], om["fy"])
         for a, b in zip(fa, fm):
             assert np.array_equal(a, b)
+
+
+def test_admission_cap_bounds_the_resident_nodes(gpu):
+    """With a cap on resident nodes the pool runs fewer simulations at once (at least one, even
+    one larger than the cap) and every result is still the one it gives alone."""
+    B = gpu
+    cases = small_requests(seed=5, n=6)
+    sizes = sorted(c.nx * c.ny for c in cases)
+    cap = sizes[0] + sizes[1]                       # at most two of the smallest fit together
+    alone = {k: run(B.Pool, [c], 1 << 30)[0][0] for k, c in enumerate(cases)}
+    capped, max_running = run(B.Pool, cases, 1 << 30, max_nodes=cap)
+    assert 1 <= max_running <= 2
+    for k in range(len(cases)):
+        (oa, fa), (oc, fc) = alone[k], capped[k]
+        assert oc["status"] == 0 and oa["mass"] == oc["mass"]
+        for a, b in zip(fa, fc):
+            assert np.array_equal(a, b)
+    tiny = run(B.Pool, cases[:2], 1 << 30, max_nodes=1)[1]   # below every request: one at a time
+    assert tiny == 1
 
 
 def test_pool_matches_single_simulation_and_oracle(gpu):
