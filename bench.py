@@ -181,6 +181,7 @@ def main():
     ap.add_argument("--steps", type=int, default=6000)
     ap.add_argument("--warmup", type=int, default=600)
     ap.add_argument("--workload", default="cylinder_wake_2048x512")
+    ap.add_argument("--storage", default="", help="storage format of the workload (default: its own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 8192 x 2048 objects")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
@@ -256,6 +257,8 @@ def main():
         "cylinder_wake_8192x2048": lambda: I.cylinder_wake_8192x2048("f32"),
     }
     case = workloads[args.workload]()
+    if args.storage:
+        case.storage = args.storage
     main_res = time_workload(case, args.steps, args.warmup)
     print(f"# {case.name}: {main_res['mlups']:.0f} MLUPS, {main_res['ms_per_step'] * 1e3:.2f} us/step",
           file=sys.stderr, flush=True)

@@ -28,8 +28,8 @@ __device__ __forceinline__ void fold_value(const StepArgs &a, long long t, int q
 }
 
 // Body forces of one row of nodes: only waves holding solid nodes do any work, one pass per
-// body id present in the wave; lane 0 adds the wave's sums into the workgroup's LDS partials.
-__device__ __forceinline__ void wave_forces(double *lds_acc, double fx, double fy, int id)
+// body id present in the wave; lane 0 adds the wave's sums into the wave's own LDS partials.
+__device__ __forceinline__ void wave_forces(double *wave_acc, double fx, double fy, int id)
 {
     unsigned long long solid = __ballot(id != 0);
     while (solid) {
@@ -39,8 +39,8 @@ __device__ __forceinline__ void wave_forces(double *lds_acc, double fx, double f
         const double sx = wave_sum(mine ? -fx : 0.0);
         const double sy = wave_sum(mine ? -fy : 0.0);
         if ((threadIdx.x & 63) == 0) {
-            atomicAdd(&lds_acc[1 + 2 * (k - 1)], sx);
-            atomicAdd(&lds_acc[2 + 2 * (k - 1)], sy);
+            wave_acc[1 + 2 * (k - 1)] += sx;
+            wave_acc[2 + 2 * (k - 1)] += sy;
         }
         solid &= ~__ballot(mine);
     }
@@ -52,15 +52,17 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
     using C = Codec<S>;
     using T = typename C::real;
     using E = typename C::elem;
-    __shared__ double lds_acc[kRingWidth];
+    // Per-wave partial sums: each wave writes only its own row (LDS accesses of one wave are in
+    // order), so the workgroup needs a single barrier, before the rows are added.
+    __shared__ double wave_acc[kBlock / 64][kRingWidth];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long t = *a.t_base + a.t_off;
     if (a.reduce) {
-        if (threadIdx.x < kRingWidth) lds_acc[threadIdx.x] = 0.0;
+        if (lane < kRingWidth) wave_acc[wave][lane] = 0.0;
         // The previous step's partials are complete (kernel boundary): fold and clear them.
         // Workgroup q's first wave folds value q (all of them if the grid is smaller).
-        if (t >= 1 && threadIdx.x < 64)
+        if (t >= 1 && wave == 0)
             for (int q = blockIdx.x; q < kRingWidth; q += gridDim.x) fold_value(a, t - 1, q, true);
-        __syncthreads();
     }
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int x = ((tile % a.ntx) << a.bx_log2) + (threadIdx.x & ((1 << a.bx_log2) - 1));
@@ -82,15 +84,16 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
             fy_d = double(m.fy);
             bad |= !(rho_d > 0.0 && rho_d < 1e30);   // also catches NaN
         }
-        if (a.reduce) wave_forces(lds_acc, fx_d, fy_d, id);
+        if (a.reduce) wave_forces(wave_acc[wave], fx_d, fy_d, id);
     }
     if (a.reduce) {
         const double mw = wave_sum(mass);
-        if ((threadIdx.x & 63) == 0) atomicAdd(&lds_acc[0], mw);
-        if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(a.status, 1u);
+        if (lane == 0) wave_acc[wave][0] = mw;
+        if (__ballot(bad) && lane == 0) atomicOr(a.status, 1u);
         __syncthreads();
         if (threadIdx.x < kRingWidth) {
-            const double v = lds_acc[threadIdx.x];
+            double v = 0.0;
+            for (int w = 0; w < kBlock / 64; w++) v += wave_acc[w][threadIdx.x];   // fixed order
             double *slot = a.acc + ((size_t)(t & 1) * kSub + (blockIdx.x & (kSub - 1))) * kRingWidth;
             if (v != 0.0) unsafeAtomicAdd(slot + threadIdx.x, v);
         }

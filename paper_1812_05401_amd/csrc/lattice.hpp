@@ -40,25 +40,38 @@ enum Storage { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3, kF32D = 4 };
 // Infinity Cache (the next step's reads come from HBM anyway, so the writes need not be cached).
 template <int S> struct Codec;
 
+// Element i of a population plane, addressed as the plane's base (uniform over the wave, held in
+// scalar registers) plus a 32-bit byte offset: the form of a global load or store with a scalar
+// base, which needs no 64-bit address arithmetic per lane.  Planes stay below 2^31 elements
+// (create rejects larger lattices), so the offset fits.
+template <typename E> __device__ __forceinline__ const E *at(const E *plane, unsigned i)
+{
+    return reinterpret_cast<const E *>(reinterpret_cast<const char *>(plane) + i * (unsigned)sizeof(E));
+}
+template <typename E> __device__ __forceinline__ E *at(E *plane, unsigned i)
+{
+    return reinterpret_cast<E *>(reinterpret_cast<char *>(plane) + i * (unsigned)sizeof(E));
+}
+
 template <> struct Codec<kF64> {
     using elem = double;
     using real = double;
-    static __device__ __forceinline__ real load(const elem *p, int i, real w) { return p[i] - w; }
-    static __device__ __forceinline__ void store(elem *p, int i, real h, real w) { p[i] = h + w; }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real w) { __builtin_nontemporal_store(h + w, p + i); }
-    static __device__ __forceinline__ double decode(const elem *p, int i, double) { return p[i]; }
-    static __device__ __forceinline__ void encode(elem *p, int i, double f, double) { p[i] = f; }
+    static __device__ __forceinline__ real load(const elem *p, unsigned i, real w) { return *at(p, i) - w; }
+    static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real w) { *at(p, i) = h + w; }
+    static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real w) { __builtin_nontemporal_store(h + w, at(p, i)); }
+    static __device__ __forceinline__ double decode(const elem *p, unsigned i, double) { return *at(p, i); }
+    static __device__ __forceinline__ void encode(elem *p, unsigned i, double f, double) { *at(p, i) = f; }
 };
 
 // binary32 h with FP32 (F32) or FP64 (F32D) arithmetic.
 template <typename R> struct CodecF32 {
     using elem = float;
     using real = R;
-    static __device__ __forceinline__ real load(const elem *p, int i, real) { return p[i]; }
-    static __device__ __forceinline__ void store(elem *p, int i, real h, real) { p[i] = float(h); }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real) { __builtin_nontemporal_store(float(h), p + i); }
-    static __device__ __forceinline__ double decode(const elem *p, int i, double w) { return double(p[i]) + w; }
-    static __device__ __forceinline__ void encode(elem *p, int i, double f, double w) { p[i] = float(f - w); }
+    static __device__ __forceinline__ real load(const elem *p, unsigned i, real) { return *at(p, i); }
+    static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real) { *at(p, i) = float(h); }
+    static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real) { __builtin_nontemporal_store(float(h), at(p, i)); }
+    static __device__ __forceinline__ double decode(const elem *p, unsigned i, double w) { return double(*at(p, i)) + w; }
+    static __device__ __forceinline__ void encode(elem *p, unsigned i, double f, double w) { *at(p, i) = float(f - w); }
 };
 template <> struct Codec<kF32> : CodecF32<float> {};
 template <> struct Codec<kF32D> : CodecF32<double> {};
@@ -66,29 +79,29 @@ template <> struct Codec<kF32D> : CodecF32<double> {};
 template <> struct Codec<kF16S> {
     using elem = _Float16;
     using real = float;
-    static __device__ __forceinline__ real load(const elem *p, int i, real) { return (float)p[i]; }
-    static __device__ __forceinline__ void store(elem *p, int i, real h, real) { p[i] = (_Float16)h; }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real)
+    static __device__ __forceinline__ real load(const elem *p, unsigned i, real) { return (float)*at(p, i); }
+    static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real) { *at(p, i) = (_Float16)h; }
+    static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real)
     {
         __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (_Float16)h),
-                                    reinterpret_cast<unsigned short *>(p + i));
+                                    reinterpret_cast<unsigned short *>(at(p, i)));
     }
-    static __device__ __forceinline__ double decode(const elem *p, int i, double w) { return double(p[i]) + w; }
-    static __device__ __forceinline__ void encode(elem *p, int i, double f, double w) { p[i] = (_Float16)(f - w); }
+    static __device__ __forceinline__ double decode(const elem *p, unsigned i, double w) { return double(*at(p, i)) + w; }
+    static __device__ __forceinline__ void encode(elem *p, unsigned i, double f, double w) { *at(p, i) = (_Float16)(f - w); }
 };
 
 template <> struct Codec<kBF16S> {
     using elem = __bf16;
     using real = float;
-    static __device__ __forceinline__ real load(const elem *p, int i, real) { return (float)p[i]; }
-    static __device__ __forceinline__ void store(elem *p, int i, real h, real) { p[i] = (__bf16)h; }
-    static __device__ __forceinline__ void store_nt(elem *p, int i, real h, real)
+    static __device__ __forceinline__ real load(const elem *p, unsigned i, real) { return (float)*at(p, i); }
+    static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real) { *at(p, i) = (__bf16)h; }
+    static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real)
     {
         __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, (__bf16)h),
-                                    reinterpret_cast<unsigned short *>(p + i));
+                                    reinterpret_cast<unsigned short *>(at(p, i)));
     }
-    static __device__ __forceinline__ double decode(const elem *p, int i, double w) { return double(p[i]) + w; }
-    static __device__ __forceinline__ void encode(elem *p, int i, double f, double w) { p[i] = (__bf16)(float)(f - w); }
+    static __device__ __forceinline__ double decode(const elem *p, unsigned i, double w) { return double(*at(p, i)) + w; }
+    static __device__ __forceinline__ void encode(elem *p, unsigned i, double f, double w) { *at(p, i) = (__bf16)(float)(f - w); }
 };
 
 // Lattice weights of Eq. 5 in the compute type.
@@ -152,10 +165,10 @@ __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__
 {
     using C = Codec<S>;
     using T = typename C::real;
-    const int P = g.pitch;
-    const int i = y * P + x;
+    const unsigned P = g.pitch;
+    const unsigned i = y * P + x;
     const bool interior = (x > 0) & (x < g.nx - 1) & (y > 0) & (y < g.ny - 1);
-    if (interior) {
+    if (interior) {                        // every index below is >= P - 1 >= 0 here
         f[0] = C::load(src, i, W<T>::rest);
         f[1] = C::load(src + 1 * g.plane, i - 1, W<T>::axis);
         f[2] = C::load(src + 2 * g.plane, i - P, W<T>::axis);
@@ -249,40 +262,45 @@ __device__ __forceinline__ Macro<T> moments(const T h[9], bool solid, T usx, T u
 // ---- collision -----------------------------------------------------------------------------------
 
 // One opposite pair (a, abar) of shifted populations with lattice weight w, c = xi_a . u and
-// xf = xi_a . f; q = -1.5 |u|^2.
-template <typename T>
+// xf = xi_a . f; q = -1.5 |u|^2.  FORCED = false drops the forcing terms, which vanish at fluid
+// nodes (f = 0 there): the same result, without their arithmetic.
+template <bool FORCED, typename T>
 __device__ __forceinline__ void collide_pair(T &ha, T &hb, T c, T xf, T w, T drho, T rho, T q,
                                              T ufp, T sp, T sm, T kp, T km)
 {
     T heq_s = w * (drho + rho * (q + T(4.5) * c * c));   // symmetric part of Eq. 4, minus w
     T heq_a = w * rho * (T(3) * c);                      // antisymmetric part of Eq. 4
-    T frc_s = w * (T(9) * c * xf - T(3) * ufp);          // symmetric part of Eq. 16
-    T frc_a = w * (T(3) * xf);                           // antisymmetric part of Eq. 16
     T hs = T(0.5) * (ha + hb);
     T hd = T(0.5) * (ha - hb);
-    T ns = hs - sp * (hs - heq_s) + kp * frc_s;
-    T na = hd - sm * (hd - heq_a) + km * frc_a;
+    T ns = hs - sp * (hs - heq_s);
+    T na = hd - sm * (hd - heq_a);
+    if (FORCED) {
+        T frc_s = w * (T(9) * c * xf - T(3) * ufp);      // symmetric part of Eq. 16
+        T frc_a = w * (T(3) * xf);                       // antisymmetric part of Eq. 16
+        ns += kp * frc_s;
+        na += km * frc_a;
+    }
     ha = ns + na;
     hb = ns - na;
 }
 
 // Two-rate collision with the split forcing term: sp/sm are the even/odd rates, kp = 1 - sp/2,
 // km = 1 - sm/2.  In place on the shifted populations h.
-template <typename T>
+template <bool FORCED, typename T>
 __device__ __forceinline__ void collide(T h[9], const Macro<T> &m, T sp, T sm, T kp, T km)
 {
     const T ux = m.ux, uy = m.uy, rho = m.rho, drho = m.drho;
     const T q = T(-1.5) * (ux * ux + uy * uy);
-    const T ufp = ux * m.fx + uy * m.fy;
+    const T ufp = FORCED ? ux * m.fx + uy * m.fy : T(0);
     {
         T heq0 = W<T>::rest * (drho + rho * q);
-        T frc0 = W<T>::rest * (T(-3) * ufp);
-        h[0] = h[0] - sp * (h[0] - heq0) + kp * frc0;
+        h[0] = h[0] - sp * (h[0] - heq0);
+        if (FORCED) h[0] += kp * (W<T>::rest * (T(-3) * ufp));
     }
-    collide_pair(h[1], h[3], ux, m.fx, W<T>::axis, drho, rho, q, ufp, sp, sm, kp, km);
-    collide_pair(h[2], h[4], uy, m.fy, W<T>::axis, drho, rho, q, ufp, sp, sm, kp, km);
-    collide_pair(h[5], h[7], ux + uy, m.fx + m.fy, W<T>::diag, drho, rho, q, ufp, sp, sm, kp, km);
-    collide_pair(h[6], h[8], uy - ux, m.fy - m.fx, W<T>::diag, drho, rho, q, ufp, sp, sm, kp, km);
+    collide_pair<FORCED>(h[1], h[3], ux, m.fx, W<T>::axis, drho, rho, q, ufp, sp, sm, kp, km);
+    collide_pair<FORCED>(h[2], h[4], uy, m.fy, W<T>::axis, drho, rho, q, ufp, sp, sm, kp, km);
+    collide_pair<FORCED>(h[5], h[7], ux + uy, m.fx + m.fy, W<T>::diag, drho, rho, q, ufp, sp, sm, kp, km);
+    collide_pair<FORCED>(h[6], h[8], uy - ux, m.fy - m.fx, W<T>::diag, drho, rho, q, ufp, sp, sm, kp, km);
 }
 
 // Equilibrium of Eq. 4 minus the weights (used to initialise); drho = rho - 1.
@@ -336,12 +354,14 @@ update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::
     T f[9];                  // shifted populations h = f - w
     pull<S>(src, x, y, g, o, f);
     if (g.inlet && x == 0) zou_he_west(f, T(p.uin_x), T(p.uin_y));
-    const int i = y * g.pitch + x;
-    id = mask[i];
+    const unsigned i = y * g.pitch + x;
+    id = *at(mask, i);
     T usx = T(0), usy = T(0);
     if (id) solid_velocity(bodies[id - 1], x, y, usx, usy);
     const Macro<T> m = moments(f, id != 0, usx, usy, T(p.k_relax), T(p.c_pen));
-    collide(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));
+    if (id) collide<true>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));   // penalized: forced
+    else collide<false>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));     // fluid: no force
+
 #pragma unroll
     for (int k = 0; k < 9; k++) {
         if (NT) C::store_nt(dst + k * g.plane, i, f[k], weight<T>(k));
