@@ -156,7 +156,9 @@ def serving_leg(n_requests, loads, budget_bytes, fifo_loads):
     return out
 
 
-def copy_probe(nbytes, reps):
+def measure_copy(nbytes, reps):
+    """Device-to-device copy of `nbytes` (torch), read + write bandwidth: the measured ceiling a
+    streaming kernel is compared with beside the datasheet peak."""
     import torch
     n = nbytes // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -165,14 +167,28 @@ def copy_probe(nbytes, reps):
         b.copy_(a)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    print(json.dumps({"copy_bytes": 4 * n, "reps": reps, "ms_per_copy": ms,
-                      "gbs_read_plus_write": 2 * 4 * n / (ms / 1e3) / 1e9}), flush=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_blit = timed(lambda: b.copy_(a))                      # the runtime's copy (blit kernel)
+    ms_ew = timed(lambda: torch.mul(a, 1.0, out=b))          # an elementwise kernel
+    del a, b
+    gbs = lambda ms: round(2 * 4 * n / (ms / 1e3) / 1e9, 1)
+    return {"copy_bytes": 4 * n, "reps": reps, "ms_blit": ms_blit, "ms_elementwise": ms_ew,
+            "gbs_blit": gbs(ms_blit), "gbs_elementwise": gbs(ms_ew),
+            "gbs_read_plus_write": max(gbs(ms_blit), gbs(ms_ew))}
+
+
+def copy_probe(nbytes, reps):
+    print(json.dumps(measure_copy(nbytes, reps)), flush=True)
 
 
 def main():
@@ -289,6 +305,20 @@ def main():
             red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "roofline")}
             print(f"# {c.name}/{st}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         line["reduced_precision"] = {"workload": "cylinder_wake_8192x2048", **red}
+        # FP32 square channels from cache-resident to far beyond the 256 MB Infinity Cache
+        sweep = []
+        for n, steps in ((2048, 400), (4096, 200), (8192, 60)):
+            c = I.cylinder_wake(n, n, d=n / 8, x0=n / 4, re=200.0, steps=steps)
+            r = time_workload(c, steps, 20)
+            sweep.append({"grid": f"{n}x{n}", "buffers_bytes": 2 * 9 * 4 * n * n,
+                          "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
+                          "frac": r["roofline"]["frac"]})
+            print(f"# square {n}x{n}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        line["square_sweep_f32"] = sweep
+        cp = measure_copy(1 << 30, 20)
+        line["copy_probe"] = cp
+        for obj in [line["roofline"], line["hbm_resident"]["roofline"]]:
+            obj["frac_of_copy"] = round(obj["achieved"] / cp["gbs_read_plus_write"], 4)
     if not args.no_serving:
         line["serving"] = serving_leg(args.serving_requests, (0.7, 1.2), 2 << 30, (0.7, 1.2))
     if not args.no_cpu_baseline:
