@@ -198,7 +198,8 @@ enum vplbm_request_state {
     VPLBM_QUEUED = 0,    /* submitted, waiting for memory or a slot */
     VPLBM_RUNNING = 1,   /* resident, advancing */
     VPLBM_DONE = 2,      /* finished; results held until vplbm_pool_result */
-    VPLBM_FAILED = 3     /* became unstable; results hold the last observables */
+    VPLBM_FAILED = 3,    /* became unstable; results hold the last observables */
+    VPLBM_CANCELLED = 4  /* cancelled; results hold the steps done (and the fields if kept) */
 };
 
 typedef struct {
@@ -243,10 +244,17 @@ int vplbm_pool_residual(vplbm_pool p, int64_t id, double *residual);
    next chunk of steps (asynchronous).  Any output pointer may be NULL. */
 int vplbm_pool_advance(vplbm_pool p, int32_t *running, int32_t *queued, int32_t *finished_total);
 
+/* Cancel a request.  A QUEUED one leaves the queue at once; a RUNNING one is retired at the next
+   vplbm_pool_advance, which releases its memory (if it finished in the launch that was in
+   flight, it is DONE instead).  Its result then has the steps done, zero mass and forces, and,
+   if it kept them and was running, the fields of its state at that point.  VPLBM_ESTATE if it
+   already finished. */
+int vplbm_pool_cancel(vplbm_pool p, int64_t id);
+
 /* State and steps done of a request. */
 int vplbm_pool_status(vplbm_pool p, int64_t id, int32_t *state, int64_t *steps_done);
 
-/* Results of a DONE or FAILED request: final observables and, if the request kept them, the
+/* Results of a DONE, FAILED or CANCELLED request: final observables and, if the request kept them, the
    host FP64 fields (nx*ny each; pass NULL to skip).  Releases the request. */
 int vplbm_pool_result(vplbm_pool p, int64_t id, vplbm_obs *out, double *rho, double *ux, double *uy);
 

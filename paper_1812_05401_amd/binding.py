@@ -87,6 +87,7 @@ SIGNATURES = [
                                      C.c_int64, C.c_int32, C.POINTER(C.c_int64)]),
     ("vplbm_pool_set_stop", C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.c_int64]),
     ("vplbm_pool_set_admission", C.c_int, [C.c_void_p, C.c_uint64]),
+    ("vplbm_pool_cancel", C.c_int, [C.c_void_p, C.c_int64]),
     ("vplbm_pool_residual", C.c_int, [C.c_void_p, C.c_int64, _dp]),
     ("vplbm_pool_advance", C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32)]),
@@ -95,7 +96,7 @@ SIGNATURES = [
     ("vplbm_pool_bytes_needed", C.c_int, [C.POINTER(Config), C.POINTER(C.c_uint64)]),
     ("vplbm_pool_destroy", C.c_int, [C.c_void_p]),
 ]
-QUEUED, RUNNING, DONE, FAILED = 0, 1, 2, 3
+QUEUED, RUNNING, DONE, FAILED, CANCELLED = 0, 1, 2, 3, 4
 
 _lib = None
 
@@ -401,6 +402,9 @@ class Pool:
         if stop is not None:
             check(load().vplbm_pool_set_stop(self.h, rid.value, float(stop[0]), int(stop[1])))
         return rid.value
+
+    def cancel(self, rid):
+        check(load().vplbm_pool_cancel(self.h, int(rid)))
 
     def set_admission(self, max_resident_nodes):
         """Cap on the resident lattice nodes (0: none)."""

@@ -248,6 +248,7 @@ struct Request {
     int keep_fields = 0;
     double tol = 0.0;
     int64_t every = 0;
+    bool cancel = false;
     double residual = INFINITY;
     int state = VPLBM_QUEUED;
     int slot = -1;
@@ -381,6 +382,7 @@ int retire(vplbm_pool p, int slot)
     r.obs.step = done - 1;
     r.obs.nbodies = (int32_t)r.bodies.size();
     r.obs.status = (d.status & 1u) ? 1 : 0;
+    const bool cancelled = r.cancel && done < d.target && !r.obs.status;
     if (done == d.target) {
         pool_fold_kernel<<<1, 64, 0, p->stream>>>(p->d_sims, slot);
         HIP_TRY(hipGetLastError());
@@ -414,7 +416,7 @@ int retire(vplbm_pool p, int slot)
             r.obs.fy[k] = d.obs[2 + 2 * k];
         }
     }
-    r.state = r.obs.status ? VPLBM_FAILED : VPLBM_DONE;
+    r.state = r.obs.status ? VPLBM_FAILED : (cancelled ? VPLBM_CANCELLED : VPLBM_DONE);
     free_request_memory(p, r);
     p->used -= r.bytes;
     p->resident_nodes -= (uint64_t)r.cfg.nx * r.cfg.ny;
@@ -690,6 +692,34 @@ int vplbm_pool_set_stop(vplbm_pool p, int64_t id, double tol, int64_t every)
     return VPLBM_OK;
 }
 
+int vplbm_pool_cancel(vplbm_pool p, int64_t id)
+{
+    if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
+    auto it = p->reqs.find(id);
+    if (it == p->reqs.end()) return fail(VPLBM_EINVAL, "unknown request %lld", (long long)id);
+    Request &r = it->second;
+    if (r.state == VPLBM_QUEUED) {
+        for (auto q = p->queue.begin(); q != p->queue.end(); ++q)
+            if (*q == id) {
+                p->queue.erase(q);
+                break;
+            }
+        memset(&r.obs, 0, sizeof r.obs);
+        r.obs.step = -1;
+        r.obs.nbodies = (int32_t)r.bodies.size();
+        r.done = 0;
+        r.state = VPLBM_CANCELLED;
+        r.keep_fields = 0;
+        p->finished++;
+        return VPLBM_OK;
+    }
+    if (r.state == VPLBM_RUNNING) {
+        r.cancel = true;
+        return VPLBM_OK;
+    }
+    return fail(VPLBM_ESTATE, "request %lld has already finished", (long long)id);
+}
+
 int vplbm_pool_set_admission(vplbm_pool p, uint64_t max_resident_nodes)
 {
     if (!pool_valid(p)) return fail(VPLBM_EINVAL, "invalid pool");
@@ -723,7 +753,7 @@ int vplbm_pool_advance(vplbm_pool p, int32_t *running, int32_t *queued, int32_t 
         if (!d.active) continue;
         const long long done = steps_done(p, d);
         p->reqs[p->slot_req[s]].done = done;
-        if (done >= d.target || (d.status & 1u)) {
+        if (done >= d.target || (d.status & 1u) || p->reqs[p->slot_req[s]].cancel) {
             int rc = retire(p, s);
             if (rc) return rc;
             changed = true;
@@ -777,7 +807,8 @@ int vplbm_pool_result(vplbm_pool p, int64_t id, vplbm_obs *out, double *rho, dou
     auto it = p->reqs.find(id);
     if (it == p->reqs.end()) return fail(VPLBM_EINVAL, "unknown request %lld", (long long)id);
     Request &r = it->second;
-    if (r.state != VPLBM_DONE && r.state != VPLBM_FAILED) return fail(VPLBM_ESTATE, "request %lld has not finished", (long long)id);
+    if (r.state != VPLBM_DONE && r.state != VPLBM_FAILED && r.state != VPLBM_CANCELLED)
+        return fail(VPLBM_ESTATE, "request %lld has not finished", (long long)id);
     if ((rho || ux || uy) && !r.keep_fields) return fail(VPLBM_EINVAL, "request %lld did not keep its fields", (long long)id);
     if (out) *out = r.obs;
     const size_t n = r.rho.size();

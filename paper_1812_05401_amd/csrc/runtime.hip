@@ -275,6 +275,7 @@ int check_config(const vplbm_config *c)
         return fail(VPLBM_EINVAL, "MRT needs Lambda > 0 (got %g)", c->lambda);
     if (!(c->eta > 0) || !isfinite(c->eta)) return fail(VPLBM_EINVAL, "eta must be > 0 (got %g)", c->eta);
     if (!(c->rho0 > 0) || !isfinite(c->rho0)) return fail(VPLBM_EINVAL, "rho0 must be > 0");
+    if (!isfinite(c->ux0) || !isfinite(c->uy0)) return fail(VPLBM_EINVAL, "initial velocity must be finite");
     const bool xper = c->bc_xlo == VPLBM_PERIODIC && c->bc_xhi == VPLBM_PERIODIC;
     const bool xio = c->bc_xlo == VPLBM_VELOCITY && (c->bc_xhi == VPLBM_OUTFLOW || c->bc_xhi == VPLBM_CONVECTIVE);
     const bool yper = c->bc_ylo == VPLBM_PERIODIC && c->bc_yhi == VPLBM_PERIODIC;

@@ -60,6 +60,7 @@ BAD = [
     (dict(nx=10, ny=10, ring=1), "ring"),
     (dict(nx=10, ny=10, bc=("velocity", "convective", "freeslip", "freeslip")), "convection speed"),
     (dict(nx=100000, ny=100000), "too large"),
+    (dict(nx=10, ny=10, u0=(float("nan"), 0.0)), "initial velocity"),
 ]
 
 
@@ -102,5 +103,6 @@ def test_null_and_foreign_handles_are_rejected():
     assert lib.vplbm_pool_set_stop(bogus, 0, 1e-6, 10) == B.EINVAL
     assert lib.vplbm_pool_residual(bogus, 0, C.byref(r)) == B.EINVAL
     assert lib.vplbm_pool_set_admission(bogus, 1000) == B.EINVAL
+    assert lib.vplbm_pool_cancel(bogus, 0) == B.EINVAL
     assert lib.vplbm_pool_advance(None, None, None, None) == B.EINVAL
     assert "invalid pool" in B.last_error()

@@ -124,3 +124,95 @@ def test_budget_and_argument_errors(gpu):
     assert max_running == 1 and len(res) == 3
     for k in range(3):
         assert res[k][0]["status"] == 0
+
+
+def _drain(pool, ids, fields):
+    from paper_1812_05401_amd import binding as B
+    out = {}
+    while len(out) < len(ids):
+        pool.advance()
+        for rid in ids:
+            if rid in out:
+                continue
+            st, done = pool.status(rid)
+            if st >= B.DONE:
+                out[rid] = (st, done, pool.result(rid, fields=fields.get(rid, False)))
+    return out
+
+
+def test_cancel_queued_and_running_requests(gpu):
+    """A request cancelled while queued never runs; one cancelled while running stops at the next
+    advance with the steps it has done; the others finish as they would alone."""
+    B = gpu
+    cases = small_requests(seed=9, n=4)
+    for c in cases:
+        c.steps = 4000                                    # long enough to be running at the cancel
+    alone = {k: run(B.Pool, [cases[k]], 1 << 30)[0][0] for k in (1, 3)}
+    pool = B.Pool(1 << 30, max_slots=2, steps_per_launch=32)
+    ids = [pool.submit(c, c.steps, keep_fields=True) for c in cases]
+    pool.advance()                                        # admits the first two
+    assert pool.status(ids[0])[0] == B.RUNNING and pool.status(ids[2])[0] == B.QUEUED
+    pool.cancel(ids[0])
+    pool.cancel(ids[2])
+    assert pool.status(ids[2])[0] == B.CANCELLED
+    res = _drain(pool, ids, {ids[0]: True, ids[1]: True, ids[3]: True})
+    with pytest.raises(B.VplbmError) as e:
+        pool.cancel(ids[1])
+    assert e.value.code in (B.EINVAL, B.ESTATE)           # released, or finished
+    pool.close()
+    st, done, (obs, fields) = res[ids[0]]
+    assert st == B.CANCELLED and 0 < done < cases[0].steps and obs["step"] == done - 1
+    assert np.all(np.isfinite(fields[0])) and obs["mass"] == 0.0
+    st, done, obs = res[ids[2]]
+    assert st == B.CANCELLED and done == 0
+    for k in (1, 3):
+        st, done, (obs, fields) = res[ids[k]]
+        oa, fa = alone[k]
+        assert st == B.DONE and done == cases[k].steps and obs["mass"] == oa["mass"]
+        for a, b in zip(fields, fa):
+            assert np.array_equal(a, b)
+
+
+def test_an_unstable_request_fails_without_affecting_the_others(gpu):
+    """Host-forced instability: an initial velocity of 50 lattice units makes the density go
+    non-positive within a few steps; that request is FAILED and released, the others finish as
+    they would alone."""
+    import copy
+    B = gpu
+    cases = small_requests(seed=13, n=3)
+    bad = copy.copy(cases[1])
+    bad.name, bad.u0 = "unstable", (50.0, 0.0)
+    alone = {k: run(B.Pool, [cases[k]], 1 << 30)[0][0] for k in (0, 2)}
+    pool = B.Pool(1 << 30, max_slots=4, steps_per_launch=32)
+    ids = [pool.submit(c, c.steps, keep_fields=True) for c in (cases[0], bad, cases[2])]
+    res = _drain(pool, ids, {ids[0]: True, ids[2]: True})
+    pool.close()
+    st, done, obs = res[ids[1]]
+    assert st == B.FAILED and obs["status"] == 1 and done < bad.steps
+    for k, rid in ((0, ids[0]), (2, ids[2])):
+        st, done, (obs, fields) = res[rid]
+        oa, fa = alone[k]
+        assert st == B.DONE and obs["mass"] == oa["mass"]
+        for a, b in zip(fields, fa):
+            assert np.array_equal(a, b)
+
+
+def test_create_and_destroy_release_device_memory(gpu):
+    import torch
+    B = gpu
+    c = small_requests(seed=2, n=1)[0]
+    for _ in range(3):                                     # let allocator caches settle
+        B.Simulation(c, stream=None).close()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(100):
+        s = B.Simulation(c, stream=None)
+        s.step(2)
+        s.residual()
+        s.close()
+        p = B.Pool(1 << 28, max_slots=2, steps_per_launch=4)
+        p.submit(c, 8)
+        p.advance()
+        p.close()
+    torch.cuda.synchronize()
+    assert abs(torch.cuda.mem_get_info()[0] - free0) < (64 << 20)
