@@ -224,7 +224,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for "
+        print(f"bench.py runs on one GPU only: there is no multi-GPU path (asked for "
               f"--gpus {args.gpus}).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
