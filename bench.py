@@ -217,7 +217,7 @@ def main():
     ap.add_argument("--stop-every", type=int, default=1000)
     ap.add_argument("--me-every", type=int, default=0,
                     help="with --precision-study: sample the momentum-exchange force every N steps")
-    ap.add_argument("--storages", default="f64,f32,f32d,f16s,bf16s",
+    ap.add_argument("--storages", default="f64,f32,f32d,f16s,f16sr,bf16s,bf16sr",
                     help="with --precision-study: storage formats to run")
     ap.add_argument("--stats-from", type=int, default=-1,
                     help="with --precision-study: first step of the statistics window (default: half)")
@@ -284,7 +284,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(main_res["ms_per_step"], 6), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "f32d": "f64", "f16s": "f32", "bf16s": "f32"}[case.storage],
+        "dtype": {"f64": "f64", "f32": "f32", "f32d": "f64", "f16s": "f32", "bf16s": "f32", "f16sr": "f32", "bf16sr": "f32"}[case.storage],
         "data": "synthetic",
         "config": {"workload": case.name, "nx": case.nx, "ny": case.ny,
                    "collision": case.collision, "storage": case.storage, "tau": case.tau,
@@ -299,7 +299,7 @@ def main():
         line["hbm_resident"] = {k: r[k] for k in ("workload", "storage", "mlups", "ms_per_step", "roofline")}
         print(f"# {big.name}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         red = {}
-        for st in ("f32", "f32d", "f16s", "bf16s"):
+        for st in ("f32", "f32d", "f16s", "f16sr", "bf16s", "bf16sr"):
             c = I.cylinder_wake_8192x2048(st)
             r = time_workload(c, 400, 40)
             red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "roofline")}

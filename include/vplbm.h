@@ -54,10 +54,17 @@ enum vplbm_collision { VPLBM_SRT = 0, VPLBM_MRT = 1 };
    even in binary32 / binary32 / binary16 / bfloat16.  Every format computes on f - w_alpha: F64
    and F32D in FP64, F32, F16S and BF16S in FP32.  F32D moves F32's bytes; only its storage is
    rounded to binary32, so long runs keep the mass and forces of an FP64 run, at some FP64
-   arithmetic cost.  get/set_populations convert to and from f in FP64; a get followed by a set
+   arithmetic cost.  F16SR and BF16SR are F16S and BF16S with stochastic rounding: each stored h
+   is rounded up or down at random with probabilities that make the rounding error zero-mean,
+   which keeps the mass of long 16-bit runs from drifting; the random bits come from a
+   counter-based hash of (node, step), so runs are reproducible.  get/set_populations convert to
+   and from f in FP64; a get followed by a set
    restores the stored bits, except that in F32 and F32D a stored |f - w_alpha| below about 2^-33
    (where FP64's rounding of f reaches half its binary32 ulp) may come back changed by < 2^-56. */
-enum vplbm_storage { VPLBM_F64 = 0, VPLBM_F32 = 1, VPLBM_F16S = 2, VPLBM_BF16S = 3, VPLBM_F32D = 4 };
+enum vplbm_storage {
+    VPLBM_F64 = 0, VPLBM_F32 = 1, VPLBM_F16S = 2, VPLBM_BF16S = 3, VPLBM_F32D = 4,
+    VPLBM_F16SR = 5, VPLBM_BF16SR = 6
+};
 
 /* Edge rules.  x edges: both PERIODIC, or VELOCITY (Zou-He inlet at x = 0 imposing (u_in_x,
    u_in_y)) with OUTFLOW (zero-gradient outlet at x = nx-1) or CONVECTIVE (the populations

@@ -5,7 +5,9 @@
 * Strouhal number St = f D / U (Eq. 23), the shedding frequency f taken from the mean period
   between linearly interpolated upward zero crossings of C_L - mean(C_L), after a moving average
   over 1/20 of the dominant period (found from the periodogram) and with hysteresis, so that
-  rounding noise on C_L cannot add crossings;
+  rounding noise on C_L cannot add crossings; and, as a cross-check that noise cannot bias, f
+  from the peak of the Hann-windowed, zero-padded periodogram (parabolic interpolation of the log
+  magnitude around the peak bin);
 * C_Dave = mean C_D and C_Lrms = rms of C_L - mean(C_L), over a window of the series.
 """
 import math
@@ -72,9 +74,26 @@ def strouhal(cl, d, u, min_periods=6):
     return d / (period * u)
 
 
+def strouhal_spectral(cl, d, u, pad=16):
+    """Eq. 23 with f at the periodogram peak: Hann window, zero padding by `pad`, and a parabola
+    through the log magnitudes of the peak bin and its neighbours.  None for a flat series."""
+    c = np.asarray(cl, dtype=np.float64)
+    c = c - c.mean()
+    n = len(c)
+    if n < 16 or not np.any(c):
+        return None
+    spec = np.abs(np.fft.rfft(c * np.hanning(n), n * pad))
+    k = int(np.argmax(spec[1:-1])) + 1
+    a, b, g = np.log(spec[k - 1:k + 2] + 1e-300)
+    den = a - 2 * b + g
+    dk = 0.5 * (a - g) / den if den != 0 else 0.0
+    return d * (k + dk) / (n * pad) / u
+
+
 def wake_statistics(fx, fy, u, d, first=0, rho=1.0):
     """C_Dave, C_Lrms and St over steps [first, end) of the per-step force series."""
     cd, cl = force_coefficients(np.asarray(fx)[first:], np.asarray(fy)[first:], u, d, rho)
     cl0 = cl - cl.mean()
     return {"C_Dave": float(cd.mean()), "C_Lrms": float(np.sqrt(np.mean(cl0 ** 2))),
-            "St": strouhal(cl, d, u), "C_Lmean": float(cl.mean()), "samples": int(len(cd))}
+            "St": strouhal(cl, d, u), "St_spectral": strouhal_spectral(cl, d, u),
+            "C_Lmean": float(cl.mean()), "samples": int(len(cd))}

@@ -19,11 +19,12 @@ RING_WIDTH = 1 + 2 * MAX_BODIES
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, EBUDGET, ESTATE = 0, -1, -2, -3, -4, -5, -6
 SRT, MRT = 0, 1
-F64, F32, F16S, BF16S, F32D = 0, 1, 2, 3, 4
+F64, F32, F16S, BF16S, F32D, F16SR, BF16SR = 0, 1, 2, 3, 4, 5, 6
 PERIODIC, VELOCITY, OUTFLOW, FREESLIP, CONVECTIVE = 0, 1, 2, 3, 4
 DISK, RECT, DISK_OUTSIDE = 0, 1, 2
 
-STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S, "f32d": F32D}
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S, "f32d": F32D, "f16sr": F16SR,
+           "bf16sr": BF16SR}
 COLLISION = {"srt": SRT, "mrt": MRT}
 BC = {"periodic": PERIODIC, "velocity": VELOCITY, "outflow": OUTFLOW, "freeslip": FREESLIP,
       "convective": CONVECTIVE}

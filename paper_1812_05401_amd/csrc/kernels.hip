@@ -77,7 +77,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if (active) {
-            const Macro<T> m = update_node<S, NT>(src, dst, a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id);
+            const Macro<T> m = update_node<S, NT>(src, dst, a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id,
+                                                  (unsigned)t);
             const double rho_d = 1.0 + double(m.drho);
             mass += rho_d;
             fx_d = double(m.fx);
@@ -152,6 +153,8 @@ hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st)
     case kF16S: VPLBM_STEP(kF16S); break;
     case kBF16S: VPLBM_STEP(kBF16S); break;
     case kF32D: VPLBM_STEP(kF32D); break;
+    case kF16SR: VPLBM_STEP(kF16SR); break;
+    case kBF16SR: VPLBM_STEP(kBF16SR); break;
     default: return hipErrorInvalidValue;
     }
 #undef VPLBM_STEP
@@ -301,6 +304,8 @@ __global__ __launch_bounds__(kBlock) void decode_kernel(StepArgs a, double *pop)
     case kF16S: kern<kF16S><<<grid, block, 0, st>>>(__VA_ARGS__); break;                        \
     case kBF16S: kern<kBF16S><<<grid, block, 0, st>>>(__VA_ARGS__); break;                      \
     case kF32D: kern<kF32D><<<grid, block, 0, st>>>(__VA_ARGS__); break;                        \
+    case kF16SR: kern<kF16SR><<<grid, block, 0, st>>>(__VA_ARGS__); break;                      \
+    case kBF16SR: kern<kBF16SR><<<grid, block, 0, st>>>(__VA_ARGS__); break;                    \
     default: return hipErrorInvalidValue;                                                        \
     }
 

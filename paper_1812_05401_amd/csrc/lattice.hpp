@@ -25,7 +25,7 @@
 
 namespace vplbm {
 
-enum Storage { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3, kF32D = 4 };
+enum Storage { kF64 = 0, kF32 = 1, kF16S = 2, kBF16S = 3, kF32D = 4, kF16SR = 5, kBF16SR = 6 };
 
 // ---- storage codecs --------------------------------------------------------------------------
 // load/store move h = f - w_a in the compute type `real`; encode/decode move f in FP64 (host
@@ -56,6 +56,7 @@ template <typename E> __device__ __forceinline__ E *at(E *plane, unsigned i)
 template <> struct Codec<kF64> {
     using elem = double;
     using real = double;
+    static constexpr bool stochastic = false;
     static __device__ __forceinline__ real load(const elem *p, unsigned i, real w) { return *at(p, i) - w; }
     static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real w) { *at(p, i) = h + w; }
     static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real w) { __builtin_nontemporal_store(h + w, at(p, i)); }
@@ -67,6 +68,7 @@ template <> struct Codec<kF64> {
 template <typename R> struct CodecF32 {
     using elem = float;
     using real = R;
+    static constexpr bool stochastic = false;
     static __device__ __forceinline__ real load(const elem *p, unsigned i, real) { return *at(p, i); }
     static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real) { *at(p, i) = float(h); }
     static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real) { __builtin_nontemporal_store(float(h), at(p, i)); }
@@ -79,6 +81,7 @@ template <> struct Codec<kF32D> : CodecF32<double> {};
 template <> struct Codec<kF16S> {
     using elem = _Float16;
     using real = float;
+    static constexpr bool stochastic = false;
     static __device__ __forceinline__ real load(const elem *p, unsigned i, real) { return (float)*at(p, i); }
     static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real) { *at(p, i) = (_Float16)h; }
     static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real)
@@ -93,6 +96,7 @@ template <> struct Codec<kF16S> {
 template <> struct Codec<kBF16S> {
     using elem = __bf16;
     using real = float;
+    static constexpr bool stochastic = false;
     static __device__ __forceinline__ real load(const elem *p, unsigned i, real) { return (float)*at(p, i); }
     static __device__ __forceinline__ void store(elem *p, unsigned i, real h, real) { *at(p, i) = (__bf16)h; }
     static __device__ __forceinline__ void store_nt(elem *p, unsigned i, real h, real)
@@ -102,6 +106,73 @@ template <> struct Codec<kBF16S> {
     }
     static __device__ __forceinline__ double decode(const elem *p, unsigned i, double w) { return double(*at(p, i)) + w; }
     static __device__ __forceinline__ void encode(elem *p, unsigned i, double f, double w) { *at(p, i) = (__bf16)(float)(f - w); }
+};
+
+// ---- stochastic rounding ---------------------------------------------------------------------
+// F16SR / BF16SR store h like F16S / BF16S but round it up or down at random, with probability
+// proportional to the distance to each neighbour, so the rounding error has zero mean.  Rounding
+// to nearest repeats the same error at every node of a uniform region, step after step, which
+// drifts the mass of long 16-bit runs; random rounding turns that drift into a random walk.
+// The random bits come from a counter-based hash of (node, step): the 32-bit finalizer of
+// MurmurHash3 (Appleby), then Marsaglia's xorshift32 for each further word.  Runs are
+// reproducible; the bits need to be unbiased, not of cryptographic quality.
+__device__ __forceinline__ unsigned mix32(unsigned h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ unsigned xorshift32(unsigned x)
+{
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x;
+}
+
+// binary16 with stochastic rounding; r holds 13 random bits (bits 0..12).  Below 2^-14 the
+// binary16 quantum is 2^-24: scale, add a uniform fraction, take the floor, scale back (all exact).
+// Above, add the random bits under the 10 kept mantissa bits of the binary32 pattern and drop them
+// (a carry moves into the exponent as it should); the result is exact in binary16.
+__device__ __forceinline__ _Float16 f16_stochastic(float v, unsigned r)
+{
+    if (__builtin_fabsf(v) < 6.103515625e-05f) {
+        const float n = __builtin_floorf(v * 16777216.0f + float(r & 0x1FFFu) * 1.220703125e-04f);
+        return (_Float16)(n * 5.9604644775390625e-08f);
+    }
+    return (_Float16)__uint_as_float((__float_as_uint(v) + (r & 0x1FFFu)) & ~0x1FFFu);
+}
+
+// bfloat16 (the top 16 bits of binary32) with stochastic rounding; r holds 16 random bits.
+__device__ __forceinline__ unsigned short bf16_stochastic_bits(float v, unsigned r)
+{
+    return (unsigned short)((__float_as_uint(v) + (r & 0xFFFFu)) >> 16);
+}
+
+template <> struct Codec<kF16SR> : Codec<kF16S> {
+    static constexpr bool stochastic = true;
+    static __device__ __forceinline__ void store_sr(elem *p, unsigned i, real h, unsigned r) { *at(p, i) = f16_stochastic(h, r); }
+    static __device__ __forceinline__ void store_sr_nt(elem *p, unsigned i, real h, unsigned r)
+    {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, f16_stochastic(h, r)),
+                                    reinterpret_cast<unsigned short *>(at(p, i)));
+    }
+};
+
+template <> struct Codec<kBF16SR> : Codec<kBF16S> {
+    static constexpr bool stochastic = true;
+    static __device__ __forceinline__ void store_sr(elem *p, unsigned i, real h, unsigned r)
+    {
+        *reinterpret_cast<unsigned short *>(at(p, i)) = bf16_stochastic_bits(h, r);
+    }
+    static __device__ __forceinline__ void store_sr_nt(elem *p, unsigned i, real h, unsigned r)
+    {
+        __builtin_nontemporal_store(bf16_stochastic_bits(h, r), reinterpret_cast<unsigned short *>(at(p, i)));
+    }
 };
 
 // Lattice weights of Eq. 5 in the compute type.
@@ -347,7 +418,7 @@ template <int S, bool NT = false>
 __device__ __forceinline__ Macro<typename Codec<S>::real>
 update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::elem *__restrict__ dst,
             const uint8_t *__restrict__ mask, const BodyState *__restrict__ bodies, const Geom &g,
-            const Outlet &o, const NodeParams &p, int x, int y, int &id)
+            const Outlet &o, const NodeParams &p, int x, int y, int &id, unsigned step)
 {
     using C = Codec<S>;
     using T = typename C::real;
@@ -362,10 +433,22 @@ update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::
     if (id) collide<true>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));   // penalized: forced
     else collide<false>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));     // fluid: no force
 
+    if constexpr (C::stochastic) {
+        // one hash per node and step, then two 16-bit words per xorshift state
+        unsigned r = mix32(i ^ mix32(step * 0x9e3779b9u + 0x7f4a7c15u));
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
-        if (NT) C::store_nt(dst + k * g.plane, i, f[k], weight<T>(k));
-        else C::store(dst + k * g.plane, i, f[k], weight<T>(k));
+        for (int k = 0; k < 9; k++) {
+            if (k % 2 == 0 && k > 0) r = xorshift32(r);
+            const unsigned bits = (k % 2) ? (r >> 16) : r;
+            if (NT) C::store_sr_nt(dst + k * g.plane, i, f[k], bits);
+            else C::store_sr(dst + k * g.plane, i, f[k], bits);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            if (NT) C::store_nt(dst + k * g.plane, i, f[k], weight<T>(k));
+            else C::store(dst + k * g.plane, i, f[k], weight<T>(k));
+        }
     }
     return m;
 }

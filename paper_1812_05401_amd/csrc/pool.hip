@@ -60,15 +60,16 @@ struct TileRef {
 };
 
 template <int S>
-__device__ __forceinline__ double pool_node(const PoolSim &d, int parity, int x, int y, double &fx,
+__device__ __forceinline__ double pool_node(const PoolSim &d, long long done, int x, int y, double &fx,
                                             double &fy, int &id)
 {
     using C = Codec<S>;
     using E = typename C::elem;
+    const int parity = (int)(done & 1);
     const E *src = static_cast<const E *>(d.buf[parity]);
     E *dst = static_cast<E *>(d.buf[parity ^ 1]);
     const Outlet none{nullptr, nullptr, 0.0};
-    const auto m = update_node<S>(src, dst, d.mask, d.bodies, d.g, none, d.p, x, y, id);
+    const auto m = update_node<S>(src, dst, d.mask, d.bodies, d.g, none, d.p, x, y, id, (unsigned)done);
     fx = double(m.fx);
     fy = double(m.fy);
     return 1.0 + double(m.drho);
@@ -90,16 +91,17 @@ __global__ __launch_bounds__(kBlock) void pool_step_kernel(PoolSim *sims, const 
     const int x = (tr.tile % d.ntx) * kPoolTileW + lane;
     const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
     const bool active = (x < d.g.nx) & (y < d.g.ny);
-    const int parity = (int)(done & 1);
     double rho = 0.0, fx = 0.0, fy = 0.0;
     int id = 0;
     if (active) {
         switch (d.storage) {
-        case kF64: rho = pool_node<kF64>(d, parity, x, y, fx, fy, id); break;
-        case kF32: rho = pool_node<kF32>(d, parity, x, y, fx, fy, id); break;
-        case kF16S: rho = pool_node<kF16S>(d, parity, x, y, fx, fy, id); break;
-        case kF32D: rho = pool_node<kF32D>(d, parity, x, y, fx, fy, id); break;
-        default: rho = pool_node<kBF16S>(d, parity, x, y, fx, fy, id); break;
+        case kF64: rho = pool_node<kF64>(d, done, x, y, fx, fy, id); break;
+        case kF32: rho = pool_node<kF32>(d, done, x, y, fx, fy, id); break;
+        case kF16S: rho = pool_node<kF16S>(d, done, x, y, fx, fy, id); break;
+        case kF32D: rho = pool_node<kF32D>(d, done, x, y, fx, fy, id); break;
+        case kF16SR: rho = pool_node<kF16SR>(d, done, x, y, fx, fy, id); break;
+        case kBF16SR: rho = pool_node<kBF16SR>(d, done, x, y, fx, fy, id); break;
+        default: rho = pool_node<kBF16S>(d, done, x, y, fx, fy, id); break;
         }
     }
     const bool bad = active && !(rho > 0.0 && rho < 1e30);
@@ -192,6 +194,8 @@ __global__ __launch_bounds__(kBlock) void pool_residual_kernel(PoolSim *sims, co
         case kF32: pool_residual_node<kF32>(d, parity, x, y, d2, u2); break;
         case kF16S: pool_residual_node<kF16S>(d, parity, x, y, d2, u2); break;
         case kF32D: pool_residual_node<kF32D>(d, parity, x, y, d2, u2); break;
+        case kF16SR: pool_residual_node<kF16SR>(d, parity, x, y, d2, u2); break;
+        case kBF16SR: pool_residual_node<kBF16SR>(d, parity, x, y, d2, u2); break;
         default: pool_residual_node<kBF16S>(d, parity, x, y, d2, u2); break;
         }
     }

@@ -41,7 +41,8 @@ int fail(int code, const char *fmt, ...)
 
 
 static_assert(kF64 == VPLBM_F64 && kF32 == VPLBM_F32 && kF16S == VPLBM_F16S &&
-                  kBF16S == VPLBM_BF16S && kF32D == VPLBM_F32D,
+                  kBF16S == VPLBM_BF16S && kF32D == VPLBM_F32D && kF16SR == VPLBM_F16SR &&
+                  kBF16SR == VPLBM_BF16SR,
               "device storage ids follow the ABI");
 
 int elem_bytes(int storage)
@@ -51,7 +52,9 @@ int elem_bytes(int storage)
     case VPLBM_F32:
     case VPLBM_F32D: return 4;
     case VPLBM_F16S:
-    case VPLBM_BF16S: return 2;
+    case VPLBM_BF16S:
+    case VPLBM_F16SR:
+    case VPLBM_BF16SR: return 2;
     default: return 0;
     }
 }

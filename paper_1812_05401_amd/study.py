@@ -59,7 +59,7 @@ def run_series(case, steps, storage=None, snapshots=(), chunk=4000, stream=None,
             "momentum_exchange": np.array(me).reshape(-1, 3)}
 
 
-def compare_storages(case, steps, storages=("f64", "f32", "f32d", "f16s", "bf16s"), snapshots=(1000, 10000),
+def compare_storages(case, steps, storages=("f64", "f32", "f32d", "f16s", "f16sr", "bf16s", "bf16sr"), snapshots=(1000, 10000),
                      stats_from=None, stream=None, log=None, dump=None, me_every=0):
     """Run `case` in every storage format and compare each with the FP64 run (and with FP32).
     `dump`: optional .npz path for the raw per-step series."""
@@ -95,7 +95,7 @@ def compare_storages(case, steps, storages=("f64", "f32", "f32d", "f16s", "bf16s
                 _, bux, buy = base["snapshots"][s]
                 ent[f"velocity_l2_vs_{base_name}_step{s}"] = A.l2_error(np.stack([ux, uy]), np.stack([bux, buy]), fluid)
             bs = A.wake_statistics(base["fx"], base["fy"], u, d, first=stats_from)
-            for k in ("C_Dave", "C_Lrms", "St"):
+            for k in ("C_Dave", "C_Lrms", "St", "St_spectral"):
                 if ent[k] is not None and bs[k]:
                     ent[f"{k}_rel_diff_vs_{base_name}"] = (ent[k] - bs[k]) / abs(bs[k])
         out["storages"][st] = ent

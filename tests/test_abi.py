@@ -39,6 +39,8 @@ def test_bytes_per_update():
     assert B.vplbm_bytes_per_update("f32d") == 73
     assert B.vplbm_bytes_per_update("f16s") == 37
     assert B.vplbm_bytes_per_update("bf16s") == 37
+    assert B.vplbm_bytes_per_update("f16sr") == 37
+    assert B.vplbm_bytes_per_update("bf16sr") == 37
     with pytest.raises(B.VplbmError):
         B.vplbm_bytes_per_update(7)
 

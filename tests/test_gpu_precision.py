@@ -43,10 +43,10 @@ def test_shifted_codec_rounds_to_nearest(gpu, storage, mant):
 
 CH = ("channel_mrt", 200, 45, "mrt", 0.56, 3 / 16, 1e-7, I.CHANNEL, (0.05, 0.0), 2, False, False)
 # measured velocity L2 (Eq. 20) vs the oracle after 1000 steps on this case, and the bounds
-BOUNDS = {"f32": 1e-5, "f32d": 1e-6, "f16s": 5e-3, "bf16s": 4e-2}
+BOUNDS = {"f32": 1e-5, "f32d": 1e-6, "f16s": 5e-3, "bf16s": 4e-2, "f16sr": 5e-3, "bf16sr": 4e-2}
 
 
-@pytest.mark.parametrize("storage", ["f32", "f32d", "f16s", "bf16s"])
+@pytest.mark.parametrize("storage", ["f32", "f32d", "f16s", "bf16s", "f16sr", "bf16sr"])
 def test_reduced_precision_against_the_oracle(gpu, storage):
     from tests.test_gpu_parity import build_case, make_pair
     case, _ = build_case(*CH, seed=17)
@@ -62,3 +62,36 @@ def test_reduced_precision_against_the_oracle(gpu, storage):
     print(f"{storage}: velocity L2 vs oracle {err:.3e}, mass {m_err:.3e}", flush=True)
     assert obs["status"] == 0
     assert err < BOUNDS[storage]
+
+
+def _ulp(x, mant_bits):
+    return 2.0 * half_ulp(x, mant_bits)
+
+
+@pytest.mark.parametrize("storage,mant", [("f16sr", 10), ("bf16sr", 7)])
+def test_stochastic_rounding_is_unbiased(gpu, storage, mant):
+    """A uniform periodic flow: every node computes the same post-collision h, in FP32 exactly as
+    an F32 run from the same populations stores it.  Rounded stochastically, each stored value is
+    one of the two 16-bit neighbours, both occur, and their mean over the 16384 nodes is within
+    5 standard errors (at most 0.02 ulp) of the FP32 value; rounding to nearest would be off by
+    the same fraction of an ulp at every node."""
+    case = I.Case("sr", 128, 128, storage=storage, bc=I.ALL_PERIODIC, u0=(0.0313, -0.0171),
+                  tau=0.7)
+    g = gpu_sim(case)
+    start = g.populations()
+    ref = gpu_sim(case, storage="f32")
+    ref.set_populations(start, 0)                      # the 16-bit values are exact in binary32
+    g.step(1)
+    ref.step(1)
+    got, want = g.populations(), ref.populations()
+    two_valued = 0
+    for k in range(9):
+        w = want[k].ravel()
+        assert np.ptp(w) == 0.0                        # uniform state: one value per plane
+        h = w[0] - W[k]
+        d = got[k].ravel() - w
+        u = _ulp(h, mant)
+        assert np.all(np.abs(d) <= u * (1 + 1e-9))
+        two_valued += len(np.unique(got[k])) == 2
+        assert abs(d.mean()) <= max(5 * u * 0.5 / np.sqrt(d.size), 1e-12 * abs(w[0]))
+    assert two_valued >= 7
