@@ -16,6 +16,9 @@ int fail(int code, const char *fmt, ...);
             return ::vplbm::fail(VPLBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
     } while (0)
 
+// Host log on stderr when the environment variable VPLBM_LOG is 1 or more (read at each call).
+void host_log(const char *fmt, ...);
+
 int elem_bytes(int storage);
 int check_config(const vplbm_config *c);
 int check_bodies(const vplbm_body *b, int n);

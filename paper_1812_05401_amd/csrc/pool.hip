@@ -421,6 +421,8 @@ int retire(vplbm_pool p, int slot)
         }
     }
     r.state = r.obs.status ? VPLBM_FAILED : (cancelled ? VPLBM_CANCELLED : VPLBM_DONE);
+    host_log("pool %p: retire request %lld (%s) after %lld steps", (void *)p, (long long)r.id,
+        r.state == VPLBM_DONE ? "done" : r.state == VPLBM_FAILED ? "failed" : "cancelled", done);
     free_request_memory(p, r);
     p->used -= r.bytes;
     p->resident_nodes -= (uint64_t)r.cfg.nx * r.cfg.ny;
@@ -498,6 +500,9 @@ int admit(vplbm_pool p, Request &r, int slot)
     r.state = VPLBM_RUNNING;
     p->used += r.bytes;
     p->resident_nodes += nodes;
+    host_log("pool %p: admit request %lld (%dx%d, %lld steps) in slot %d, %llu bytes; resident %llu nodes",
+        (void *)p, (long long)r.id, r.cfg.nx, r.cfg.ny, (long long)r.nsteps, slot,
+        (unsigned long long)r.bytes, (unsigned long long)p->resident_nodes);
     return 1;
 }
 
@@ -515,6 +520,8 @@ int ensure_pool_graph(vplbm_pool p)
     int cap = 4096;
     while (cap < p->ntiles) cap *= 2;
     p->grid_cap = cap;
+    host_log("pool %p: capture the step graph (%d workgroups per launch, %d steps, residual checks %d)",
+        (void *)p, cap, p->cfg.steps_per_launch, (int)checks);
     if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -40,6 +40,18 @@ int fail(int code, const char *fmt, ...)
 
 
 
+void host_log(const char *fmt, ...)
+{
+    const char *e = getenv("VPLBM_LOG");
+    if (!e || atoi(e) < 1) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[vplbm] %s\n", buf);
+}
+
 static_assert(kF64 == VPLBM_F64 && kF32 == VPLBM_F32 && kF16S == VPLBM_F16S &&
                   kBF16S == VPLBM_BF16S && kF32D == VPLBM_F32D && kF16SR == VPLBM_F16SR &&
                   kBF16SR == VPLBM_BF16SR,
@@ -403,6 +415,9 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     }
     track(s, true);
     *out = s;
+    host_log("create %p: %dx%d storage %d collision %d, tiles %dx%d x %d rows, %d planes of %d elements, "
+        "non-temporal stores %d", (void *)s, g.nx, g.ny, s->storage, cfg->collision,
+        1 << s->ts.bx_log2, s->ts.by, s->ts.rows, 9, g.plane, s->nt_store);
     return VPLBM_OK;
 }
 
@@ -410,6 +425,7 @@ int vplbm_destroy(vplbm_sim s)
 {
     if (!s) return VPLBM_OK;
     if (!valid(s)) return fail(VPLBM_EINVAL, "invalid handle");
+    host_log("destroy %p after %lld steps", (void *)s, (long long)s->steps);
     release(s);
     return VPLBM_OK;
 }

@@ -216,3 +216,19 @@ def test_create_and_destroy_release_device_memory(gpu):
         p.close()
     torch.cuda.synchronize()
     assert abs(torch.cuda.mem_get_info()[0] - free0) < (64 << 20)
+
+
+def test_host_log(gpu, capfd, monkeypatch):
+    """VPLBM_LOG=1 logs creation, admission, graph capture and retirement on stderr."""
+    B = gpu
+    monkeypatch.setenv("VPLBM_LOG", "1")
+    c = small_requests(seed=4, n=1)[0]
+    B.Simulation(c, stream=None).close()
+    run(B.Pool, [c], 1 << 30)
+    err = capfd.readouterr().err
+    for word in ("[vplbm] create", "[vplbm] destroy", "admit request", "capture the step graph",
+                 "retire request"):
+        assert word in err, word
+    monkeypatch.setenv("VPLBM_LOG", "0")
+    B.Simulation(c, stream=None).close()
+    assert "[vplbm]" not in capfd.readouterr().err
