@@ -232,3 +232,17 @@ def test_host_log(gpu, capfd, monkeypatch):
     monkeypatch.setenv("VPLBM_LOG", "0")
     B.Simulation(c, stream=None).close()
     assert "[vplbm]" not in capfd.readouterr().err
+
+
+@pytest.mark.parametrize("storage", ["f16sr", "bf16sr"])
+def test_stochastic_rounding_is_the_same_in_the_pool(gpu, storage):
+    """The random bits depend on the node and on the steps the simulation has run, so a pool run
+    equals the single-simulation run bit for bit."""
+    B = gpu
+    c = small_requests(seed=21, n=1, storage=storage)[0]
+    (obs, (rho, ux, uy)) = run(B.Pool, [c], 1 << 30)[0][0]
+    s = B.Simulation(c, stream=None)
+    s.step(c.steps)
+    _, srho, sux, suy = s.observables(fields=True)
+    s.close()
+    assert np.array_equal(rho, srho) and np.array_equal(ux, sux) and np.array_equal(uy, suy)
