@@ -2,8 +2,9 @@
 //
 // The step is one fused, memory-bound pass: per node 9 pulled population loads, a 1-byte mask
 // load, the moments / penalization / collision in registers, 9 coalesced stores, and the FP64
-// per-step reductions (wave64 shuffles, one LDS hop, FP64 atomics into a device ring).  Nothing
-// here is a dense contraction, so there is no MFMA; the roofline is HBM bandwidth.
+// per-step reductions (wave64 shuffles, one LDS hop, FP64 atomics into sub-slots that the next
+// step folds into a device ring).  Nothing here is a dense contraction, so there is no MFMA; the
+// roofline is HBM bandwidth.
 #include <stdlib.h>
 
 #include "kernels.hpp"

@@ -1,5 +1,5 @@
-// Serving pool: many resident VP-LBM simulations advanced together by one persistent batched
-// kernel replayed from a captured HIP graph (see the pool section of include/vplbm.h).
+// Serving pool: many resident VP-LBM simulations advanced together by a batched step kernel
+// replayed from a captured HIP graph (see the pool section of include/vplbm.h).
 //
 // Device side.  A descriptor per slot (buffers, geometry, parameters, admission step, target) and
 // a table of 64 x 4 tiles covering every resident simulation.  One workgroup per tile; each tile
@@ -11,10 +11,15 @@
 // retirement a fold kernel adds the tiles in tile order, so the final observables are bitwise
 // independent of the mix.
 //
-// Host side.  Between graph replays: retire finished simulations (fold, copy results, free
-// memory), admit queued requests first come first served while the memory budget and slots
-// allow, rebuild the tile table.  The graph reads the tables from device memory; it is captured
-// again only when the tile count outgrows its grid.
+// Early stop: for simulations that ask for it, the graph ends with a residual check (a per-tile
+// kernel and a per-slot fold) that lowers the simulation's target on the device once its
+// velocity change is below the tolerance.
+//
+// Host side.  Between graph replays: retire finished, failed and cancelled simulations (fold,
+// copy results, free memory), admit queued requests first come first served while the memory
+// budget, the slots and the resident-node cap allow, rebuild the tile table.  The graph reads the
+// tables from device memory; it is captured again only when the tile count outgrows its grid or
+// the residual check is switched on or off.
 #include <math.h>
 #include <stddef.h>
 #include <string.h>
