@@ -215,6 +215,25 @@ def test_full_size_paper_cylinder_re500(gpu):
     assert eg < 1e-5 and er < 1e-5 and eu < 1e-4 and em < 1e-6 and ef < 1e-4
 
 
+def test_full_size_oscillating_cylinder_8192x2048(gpu):
+    """The 8192 x 2048 oscillating cylinder at its full size in the launch configuration the
+    benchmark times (non-temporal stores, mask rebuilt on the device every step), 3 steps from the
+    uniform start: FP64 against the oracle to 1e-12, FP32 and FP16S to their rounding."""
+    case = I.oscillating_cylinder_8192x2048()
+    o = oracle_sim(case)
+    o.step(3)
+    for storage, tol in (("f64", None), ("f32", (1e-5, 1e-4)), ("f16s", (2e-3, 2e-2))):
+        g = gpu_sim(case, storage=storage)
+        g.step(3)
+        errs = compare(o, g, TOL64 if tol is None else 0, f"oscillating_8192x2048_{storage}")
+        g.close()
+        if tol is None:
+            assert max(errs) <= TOL64
+        else:
+            eg, er, eu, em, ef = errs
+            assert eg < tol[0] and er < tol[0] and eu < tol[1] and em < tol[0] and ef < tol[1]
+
+
 ME_CASES = [CASES[i] for i in (0, 2, 5, 13)]
 
 
