@@ -255,3 +255,25 @@ def test_momentum_exchange_matches_oracle(gpu, spec):
     err = max(np.max(np.abs(gfx - ofx)), np.max(np.abs(gfy - ofy))) / sc
     print(f"{spec[0]}: momentum exchange {ofx} {ofy}, rel {err:.2e}", flush=True)
     assert err <= TOL64
+
+
+def test_largest_lattice_the_abi_accepts(gpu):
+    """Edge of the 32-bit plane offsets: the largest 16384-wide lattice create accepts (9 planes of
+    just under 2^31 / 9 elements, 8.6 GB per FP32 buffer) runs a uniform periodic flow that stays
+    uniform with its mass kept; one more row is refused.  Zero steps is a no-op."""
+    from paper_1812_05401_amd import binding as B
+    nx = 16384
+    ny = ((1 << 31) - 64 * 9) // (9 * nx)
+    while nx * ny * 9 + 64 * 9 >= (1 << 31):
+        ny -= 1
+    with pytest.raises(B.VplbmError):
+        B.vplbm_create(B.make_config(nx, ny + 1))
+    case = I.Case("largest", nx, ny, storage="f32", bc=I.ALL_PERIODIC, u0=(0.02, -0.01), tau=0.8)
+    s = gpu_sim(case)
+    s.step(0)
+    assert s.steps_done == 0
+    s.step(2)
+    obs = s.observables()
+    s.close()
+    assert obs["status"] == 0 and obs["step"] == 1
+    assert abs(obs["mass"] / (nx * ny) - 1.0) < 1e-6
