@@ -273,7 +273,9 @@ def vplbm_bytes_per_update(storage):
 class Simulation:
     """A simulation on the GPU.  ``case`` is a paper_1812_05401_amd.inputs.Case (or pass the
     config fields as keywords).  ``stream``: hipStream_t as an int, 'torch' for torch's current
-    stream, or None for a stream owned by the library."""
+    stream, or None for a stream owned by the library.  ``device_mask``: rasterize the case's
+    bodies on the device (True), or leave the lattice all fluid until ``set_mask(body_id,
+    bodies)`` gives a host mask (False)."""
 
     def __init__(self, case=None, stream="torch", reduce=True, ring=0, device_mask=True, **kw):
         if stream == "torch":
@@ -286,16 +288,16 @@ class Simulation:
         self.nx, self.ny = self.cfg.nx, self.cfg.ny
         self.h = vplbm_create(self.cfg)
         self.nbodies = 0
-        if case is not None and case.bodies:
-            self.set_mask(None if device_mask else "host", case.bodies)
+        if case is not None and case.bodies and device_mask:
+            self.set_mask(None, case.bodies)
 
     @property
     def shape(self):
         return (self.ny, self.nx)
 
     def set_mask(self, body_id, bodies):
-        if isinstance(body_id, str):
-            raise ValueError("pass a body-id array or None")
+        """body_id: a [ny, nx] uint8 array of body ids (0 = fluid), or None to rasterize
+        ``bodies`` on the device."""
         vplbm_set_mask(self.h, body_id, bodies)
         self.nbodies = len(bodies)
 

@@ -59,7 +59,7 @@ def make_pair(case, ids, seed, storage="f64"):
     if ids is not None:
         o.set_mask(ids)
     o.init_fields(*fields)
-    g = gpu_sim(case, storage=storage, device_mask=True)
+    g = gpu_sim(case, storage=storage, device_mask=ids is None)
     if ids is not None:
         g.set_mask(ids, case.bodies)
     g.init_fields(*fields)
