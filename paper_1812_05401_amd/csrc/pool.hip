@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "pool_policy.hpp"
 
 using namespace vplbm;
 
@@ -442,9 +443,9 @@ int retire(vplbm_pool p, int slot)
 // not fit now, < 0 on error.
 int admit(vplbm_pool p, Request &r, int slot)
 {
-    if (p->used + r.bytes > p->cfg.budget_bytes) return 0;
     const uint64_t nodes = (uint64_t)r.cfg.nx * r.cfg.ny;
-    if (p->max_nodes && p->resident_nodes > 0 && p->resident_nodes + nodes > p->max_nodes) return 0;
+    const AdmissionState st{p->used, p->cfg.budget_bytes, p->resident_nodes, p->max_nodes, 1};
+    if (!may_admit(st, r.bytes, nodes)) return 0;
     PoolSim d{};
     pool_geometry(r.cfg, d.g, d.ntx, d.ntiles);
     const size_t pop = (size_t)9 * d.g.plane * elem_bytes(r.cfg.storage);
