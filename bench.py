@@ -299,7 +299,7 @@ def main():
         line["hbm_resident"] = {k: r[k] for k in ("workload", "storage", "mlups", "ms_per_step", "roofline")}
         print(f"# {big.name}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         red = {}
-        for st in ("f32", "f32d", "f16s", "f16sr", "bf16s", "bf16sr"):
+        for st in ("f64", "f32", "f32d", "f16s", "f16sr", "bf16s", "bf16sr"):
             c = I.cylinder_wake_8192x2048(st)
             r = time_workload(c, 400, 40)
             red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "roofline")}
