@@ -13,19 +13,61 @@ namespace vplbm {
 
 // ---- the fused step --------------------------------------------------------------------------
 
-// Sum value q of the sub-slots [kSub][kRingWidth] of step t into ring entry t, with one wave:
-// lane l adds sub-slots l, l + 64, ... in order, then a fixed butterfly adds the lanes, so the
-// result does not depend on which workgroup folds or when.  One memory round trip, not kSub.
-__device__ __forceinline__ void fold_value(const StepArgs &a, long long t, int q, bool clear)
+// Sub-slots [kSub][kRingWidth] of step t: one of kAccSets sets, used round-robin by step.
+__device__ __forceinline__ double *acc_set(const StepArgs &a, long long t)
 {
-    double *acc = a.acc + (size_t)(t & 1) * kSub * kRingWidth;
+    return a.acc + (size_t)(t & (kAccSets - 1)) * kSub * kRingWidth;
+}
+
+// Sum value q of the sub-slots of steps t - 2 and t - 1 (those that exist) into their ring
+// entries, with one wave: lane l adds sub-slots l, l + 64, ... in order, then a fixed butterfly
+// adds the lanes, so a result does not depend on which workgroup folds or when.  One memory round
+// trip for both steps.  Nothing is cleared, so folding a step again gives the same value: a step
+// is folded by the next launch and, when that launch starts one step later, by the one after.
+__device__ __forceinline__ void fold_recent(const StepArgs &a, long long t, int q)
+{
     const int lane = threadIdx.x & 63;
-    double v = 0.0;
-    for (int b = lane; b < kSub; b += 64) v += acc[b * kRingWidth + q];
-    v = wave_sum(v);
-    if (lane == 0) a.ring[(size_t)(t % a.ring_len) * kRingWidth + q] = v;
-    if (clear)
-        for (int b = lane; b < kSub; b += 64) acc[b * kRingWidth + q] = 0.0;
+    const double *s1 = acc_set(a, t - 1), *s2 = acc_set(a, t - 2);
+    double v1 = 0.0, v2 = 0.0;
+    for (int b = lane; b < kSub; b += 64) {
+        v1 += s1[b * kRingWidth + q];
+        v2 += s2[b * kRingWidth + q];
+    }
+    v1 = wave_sum(v1);
+    v2 = wave_sum(v2);
+    if (lane == 0) {
+        if (t >= 1) a.ring[(size_t)((t - 1) % a.ring_len) * kRingWidth + q] = v1;
+        if (t >= 2) a.ring[(size_t)((t - 2) % a.ring_len) * kRingWidth + q] = v2;
+    }
+}
+
+// Start of a launch that computes steps t .. t + n - 1 (n = 1 or 2): workgroup q's first wave
+// folds value q of steps t - 2 and t - 1, and workgroup b zeroes sub-slot b of the sets of steps
+// t + n and t + n + 1, which the next launch accumulates into.  With kAccSets = 8, the sets
+// folded, written and cleared by one launch are distinct, and a set is cleared only after every
+// fold of its previous step (its launch and the next two have run).
+__device__ __forceinline__ void reduction_prologue(const StepArgs &a, long long t, int n)
+{
+    if (threadIdx.x < 64)
+        for (int q = blockIdx.x; q < kRingWidth; q += gridDim.x) fold_recent(a, t, q);
+    if (threadIdx.x < 2 * kRingWidth) {
+        double *set = acc_set(a, t + n + threadIdx.x / kRingWidth);
+        const int q = threadIdx.x % kRingWidth;
+        for (int b = blockIdx.x; b < kSub; b += gridDim.x) set[b * kRingWidth + q] = 0.0;
+    }
+}
+
+// A workgroup's partial sums of step t (rows of per-wave partials, added in a fixed order) into
+// its sub-slot of the step's set: threads 0 .. kRingWidth - 1, after the barrier that completes
+// the rows.
+__device__ __forceinline__ void add_partials(const StepArgs &a, long long t, const double *rows, int nrows)
+{
+    if (threadIdx.x < kRingWidth) {
+        double v = 0.0;
+        for (int w = 0; w < nrows; w++) v += rows[w * kRingWidth + threadIdx.x];   // fixed order
+        double *slot = acc_set(a, t) + (blockIdx.x & (kSub - 1)) * kRingWidth;
+        if (v != 0.0) unsafeAtomicAdd(slot + threadIdx.x, v);
+    }
 }
 
 // Body forces of one row of nodes: only waves holding solid nodes do any work, one pass per
@@ -60,10 +102,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
     const long long t = *a.t_base + a.t_off;
     if (a.reduce) {
         if (lane < kRingWidth) wave_acc[wave][lane] = 0.0;
-        // The previous step's partials are complete (kernel boundary): fold and clear them.
-        // Workgroup q's first wave folds value q (all of them if the grid is smaller).
-        if (t >= 1 && wave == 0)
-            for (int q = blockIdx.x; q < kRingWidth; q += gridDim.x) fold_value(a, t - 1, q, true);
+        reduction_prologue(a, t, 1);   // earlier steps' partials are complete (kernel boundary)
     }
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int x = ((tile % a.ntx) << a.bx_log2) + (threadIdx.x & ((1 << a.bx_log2) - 1));
@@ -93,20 +132,132 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
         if (lane == 0) wave_acc[wave][0] = mw;
         if (__ballot(bad) && lane == 0) atomicOr(a.status, 1u);
         __syncthreads();
-        if (threadIdx.x < kRingWidth) {
-            double v = 0.0;
-            for (int w = 0; w < kBlock / 64; w++) v += wave_acc[w][threadIdx.x];   // fixed order
-            double *slot = a.acc + ((size_t)(t & 1) * kSub + (blockIdx.x & (kSub - 1))) * kRingWidth;
-            if (v != 0.0) unsafeAtomicAdd(slot + threadIdx.x, v);
+        add_partials(a, t, &wave_acc[0][0], kBlock / 64);
+    }
+}
+
+// ---- two steps per launch ----------------------------------------------------------------------
+// Steps t and t + 1 of a TW x TH tile in one launch.  Phase 1 computes step t on the tile and its
+// one-node halo, from the planes in global memory, and keeps the result in LDS in the storage
+// format, rounded exactly as a store to global memory would round it; phase 2 computes step t + 1
+// of the tile from LDS and stores it.  Each node's arithmetic is the one-step kernel's, so the
+// populations are bitwise those of two one-step launches, with one read and one write of the
+// planes instead of two of each.  The halo is computed twice (by this tile and its neighbour):
+// (TW + 2)(TH + 2) / (TW TH) of the nodes in phase 1.  Static masks only (bodies at rest or
+// spinning in place), and no convective outlet: the host falls back to one step per launch.
+template <int S> struct Tile2 {
+    static constexpr int w = 128, h = 8;       // 4-byte and 2-byte storage: 46.8 / 23.4 KB of LDS
+};
+template <> struct Tile2<kF64> {
+    static constexpr int w = 64, h = 8;        // 8-byte storage: 47.5 KB of LDS
+};
+
+template <int S, bool NT>
+__global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    using E = typename C::elem;
+    constexpr int TW = Tile2<S>::w, TH = Tile2<S>::h, EW = TW + 2, EN = EW * (TH + 2);
+    constexpr int NW = kBlock2 / 64;
+    static_assert((TW * TH) % kBlock2 == 0, "phase 2 gives every thread the same number of nodes");
+    __shared__ E mid[9 * EN];                      // step t on the tile and its halo
+    __shared__ double wave_acc[2][NW][kRingWidth]; // per-wave partials of steps t and t + 1
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long t = *a.t_base + a.t_off;
+    const Geom &g = a.g;
+    if (a.reduce) {
+        if (lane < kRingWidth) {
+            wave_acc[0][wave][lane] = 0.0;
+            wave_acc[1][wave][lane] = 0.0;
         }
+        reduction_prologue(a, t, 2);
+    }
+    const int ntx = (g.nx + TW - 1) / TW;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * TW, y0 = (tile / ntx) * TH;
+    const E *__restrict__ src = static_cast<const E *>(a.src);
+    E *__restrict__ dst = static_cast<E *>(a.dst);
+    bool bad = false;
+    double mass = 0.0;
+
+    // Phase 1.  Halo nodes across a periodic edge are the wrapped nodes; halo positions outside
+    // a non-periodic edge (and beyond a ragged tile) are skipped: no phase-2 pull reads them.
+    for (int it = 0; it < (EN + kBlock2 - 1) / kBlock2; it++) {
+        const int e = threadIdx.x + it * kBlock2;
+        const int lx = e % EW - 1, ly = e / EW - 1;
+        const int ux = x0 + lx, uy = y0 + ly;     // unwrapped
+        int x = ux, y = uy;
+        bool live = e < EN;
+        if (x < 0 || x >= g.nx) {
+            if (g.xper && x >= -1 && x <= g.nx) x += x < 0 ? g.nx : -g.nx;
+            else live = false;
+        }
+        if (y < 0 || y >= g.ny) {
+            if (g.yper && y >= -1 && y <= g.ny) y += y < 0 ? g.ny : -g.ny;
+            else live = false;
+        }
+        const bool own = live & (lx >= 0) & (lx < TW) & (ly >= 0) & (ly < TH) & (ux < g.nx) & (uy < g.ny);
+        double fx_d = 0.0, fy_d = 0.0;
+        int id = 0;
+        if (live) {
+            T f[9];
+            pull<S>(src, x, y, g, a.outlet, f);
+            const Macro<T> m = relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
+            store_node<S>(mid, EN, unsigned(e), f, unsigned(y * g.pitch + x), (unsigned)t);
+            if (own) {
+                const double rho_d = 1.0 + double(m.drho);
+                mass += rho_d;
+                fx_d = double(m.fx);
+                fy_d = double(m.fy);
+                bad |= !(rho_d > 0.0 && rho_d < 1e30);
+            } else {
+                id = 0;                           // another tile's node: not in this tile's sums
+            }
+        }
+        if (a.reduce) wave_forces(wave_acc[0][wave], fx_d, fy_d, id);
+    }
+    if (a.reduce) {
+        const double mw = wave_sum(mass);
+        if (lane == 0) wave_acc[0][wave][0] = mw;
+    }
+    mass = 0.0;
+    __syncthreads();                              // the tile of step t is complete
+    if (a.reduce) add_partials(a, t, &wave_acc[0][0][0], NW);
+
+    // Phase 2.
+    for (int it = 0; it < TW * TH / kBlock2; it++) {
+        const int j = threadIdx.x + it * kBlock2;
+        const int x = x0 + j % TW, y = y0 + j / TW;
+        double fx_d = 0.0, fy_d = 0.0;
+        int id = 0;
+        if ((x < g.nx) & (y < g.ny)) {
+            T f[9];
+            pull_tile<S>(mid, EN, EW, x, y, x0, y0, g, f);
+            const Macro<T> m = relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
+            const unsigned i = y * g.pitch + x;
+            store_node<S, NT>(dst, g.plane, i, f, i, (unsigned)(t + 1));
+            const double rho_d = 1.0 + double(m.drho);
+            mass += rho_d;
+            fx_d = double(m.fx);
+            fy_d = double(m.fy);
+            bad |= !(rho_d > 0.0 && rho_d < 1e30);
+        }
+        if (a.reduce) wave_forces(wave_acc[1][wave], fx_d, fy_d, id);
+    }
+    if (a.reduce) {
+        const double mw = wave_sum(mass);
+        if (lane == 0) wave_acc[1][wave][0] = mw;
+        if (__ballot(bad) && lane == 0) atomicOr(a.status, 1u);
+        __syncthreads();
+        add_partials(a, t + 1, &wave_acc[1][0][0], NW);
     }
 }
 
 __global__ void fold_kernel(StepArgs a)
 {
     const long long t = *a.t_base;
-    if (t >= 1)
-        for (int q = 0; q < kRingWidth; q++) fold_value(a, t - 1, q, false);
+    for (int q = 0; q < kRingWidth; q++) fold_recent(a, t, q);
 }
 
 hipError_t launch_fold(const StepArgs &a, hipStream_t st)
@@ -159,6 +310,37 @@ hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st)
     default: return hipErrorInvalidValue;
     }
 #undef VPLBM_STEP
+    return hipGetLastError();
+}
+
+// Tiles of the two-step kernel along x and y.
+static void tiles2(int storage, const Geom &g, int &ntx, int &nty)
+{
+    const int tw = storage == kF64 ? Tile2<kF64>::w : Tile2<kF32>::w;
+    const int th = storage == kF64 ? Tile2<kF64>::h : Tile2<kF32>::h;
+    ntx = (g.nx + tw - 1) / tw;
+    nty = (g.ny + th - 1) / th;
+}
+
+hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st)
+{
+    int ntx, nty;
+    tiles2(storage, a.g, ntx, nty);
+    const dim3 grid(ntx * nty), block(kBlock2);
+#define VPLBM_STEP2(S)                                                                            \
+    (a.nt_store ? step2_kernel<S, true><<<grid, block, 0, st>>>(a)                                  \
+                : step2_kernel<S, false><<<grid, block, 0, st>>>(a))
+    switch (storage) {
+    case kF64: VPLBM_STEP2(kF64); break;
+    case kF32: VPLBM_STEP2(kF32); break;
+    case kF16S: VPLBM_STEP2(kF16S); break;
+    case kBF16S: VPLBM_STEP2(kBF16S); break;
+    case kF32D: VPLBM_STEP2(kF32D); break;
+    case kF16SR: VPLBM_STEP2(kF16SR); break;
+    case kBF16SR: VPLBM_STEP2(kBF16SR); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef VPLBM_STEP2
     return hipGetLastError();
 }
 

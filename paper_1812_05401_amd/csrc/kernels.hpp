@@ -11,11 +11,14 @@ namespace vplbm {
 constexpr int kMaxBodies = 8;
 constexpr int kRingWidth = 1 + 2 * kMaxBodies;   // mass, (fx, fy) per body
 constexpr int kBlock = 256;                      // threads per workgroup (4 wave64)
+constexpr int kBlock2 = 512;                     // the two-step kernel's workgroup (8 wave64)
 // Per-step reductions go through kSub sub-slots: workgroup b adds its partials into sub-slot
 // b % kSub, so no address takes more than 1/kSub of the atomics (device-scope FP64 atomics to
-// one address serialize).  The next step's first workgroup (or the fold kernel at observation
-// time) sums the sub-slots in a fixed order into the ring.
+// one address serialize).  The next launch's first workgroups (or the fold kernel at observation
+// time) sum the sub-slots in a fixed order into the ring.  Steps use kAccSets sets of sub-slots
+// round-robin, so that a two-step launch can fold the steps before it while it adds into its own.
 constexpr int kSub = 64;
+constexpr int kAccSets = 8;
 
 struct BodyParams {          // as given by the caller (vplbm_body), device copy
     int kind;                // 0 disk, 1 rect, 2 outside of a disk
@@ -29,7 +32,7 @@ struct StepArgs {
     const uint8_t *mask;     // body id per node (pitch = geometry pitch)
     const BodyState *bodies; // body state at this step's time
     double *ring;            // [ring_len][kRingWidth] per-step observables
-    double *acc;             // [2][kSub][kRingWidth] partial sums of the last two steps
+    double *acc;             // [kAccSets][kSub][kRingWidth] per-step partial sums
     unsigned *status;        // bit 0: non-finite or non-positive density seen
     const long long *t_base; // step counter on the device
     Geom g;
@@ -50,6 +53,9 @@ struct TileShape {
 TileShape tile_shape(int nx, int ny, int elem_bytes);
 
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st);
+// Steps *t_base + t_off and the one after in one launch, from a.src into a.dst (static mask, no
+// convective outlet).
+hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st);
 
 // Per-node density and penalized velocity of the current state into dense FP64 arrays.
 hipError_t launch_readback(int storage, const StepArgs &a, double *rho, double *ux, double *uy,
@@ -84,7 +90,7 @@ hipError_t launch_residual(int storage, const StepArgs &a, double *snap, double 
 hipError_t launch_momentum_exchange(int storage, const StepArgs &a, double *out, hipStream_t st);
 // Convective outlet: prev = the last column's populations 3, 6, 7 of the state a.src.
 hipError_t launch_outlet_init(int storage, const StepArgs &a, void *prev, hipStream_t st);
-// Sum the sub-slots of step *t_base - 1 into its ring entry (without clearing them).
+// Sum the sub-slots of steps *t_base - 2 and *t_base - 1 into their ring entries.
 hipError_t launch_fold(const StepArgs &a, hipStream_t st);
 hipError_t launch_fill_f64(double *p, size_t n, double v, hipStream_t st);
 hipError_t launch_fill_u32(unsigned *p, size_t n, unsigned v, hipStream_t st);

@@ -277,6 +277,46 @@ __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__
     }
 }
 
+// Pull the nine shifted populations h of node (x, y) from a workgroup's tile in LDS instead of the
+// planes in global memory.  The tile holds the post-collision populations of the nodes
+// [x0 - 1, x0 + ew - 2] x [y0 - 1, ...] in unwrapped coordinates, ew per row, `plane` elements
+// per population: a periodic neighbour across an edge sits in the tile's halo, so for the tile
+// only the free-slip and clamped edges of edge_source remain.  Every node the pull reads lies
+// within one node of (x, y), inside the tile.
+template <int S>
+__device__ __forceinline__ void pull_tile(const typename Codec<S>::elem *tile, unsigned plane, int ew,
+                                          int x, int y, int x0, int y0, const Geom &g,
+                                          typename Codec<S>::real f[9])
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    const unsigned e = unsigned((y - y0 + 1) * ew + (x - x0 + 1));
+    const unsigned E = unsigned(ew);
+    const bool shifts = (g.xper | ((x > 0) & (x < g.nx - 1))) & (g.yper | ((y > 0) & (y < g.ny - 1)));
+    if (shifts) {                          // every index below is >= 0 (the tile has a halo)
+        f[0] = C::load(tile, e, W<T>::rest);
+        f[1] = C::load(tile + 1 * plane, e - 1, W<T>::axis);
+        f[2] = C::load(tile + 2 * plane, e - E, W<T>::axis);
+        f[3] = C::load(tile + 3 * plane, e + 1, W<T>::axis);
+        f[4] = C::load(tile + 4 * plane, e + E, W<T>::axis);
+        f[5] = C::load(tile + 5 * plane, e - E - 1, W<T>::diag);
+        f[6] = C::load(tile + 6 * plane, e - E + 1, W<T>::diag);
+        f[7] = C::load(tile + 7 * plane, e + E + 1, W<T>::diag);
+        f[8] = C::load(tile + 8 * plane, e + E - 1, W<T>::diag);
+    } else {
+        constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+        constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+        constexpr int mirror_y[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+#pragma unroll
+        for (int a = 0; a < 9; a++) {
+            int sx = x - cx[a], sy = y - cy[a], pa = a;
+            if ((sy < 0 || sy >= g.ny) && !g.yper) { sy = y; pa = mirror_y[a]; }
+            if ((sx < 0 || sx >= g.nx) && !g.xper) sx = sx < 0 ? 0 : g.nx - 1;
+            f[a] = C::load(tile + pa * plane, unsigned((sy - y0 + 1) * ew + (sx - x0 + 1)), weight<T>(a));
+        }
+    }
+}
+
 // Zou-He velocity inlet on the west edge: the populations entering from x < 0 (1, 5, 8) are set
 // so that sum f = rho and sum xi f = rho (ux, uy), with rho from the known populations and the
 // non-equilibrium parts bounced back.  On h: the known weights w0 + w2 + w4 + 2 (w3 + w6 + w7)
@@ -412,6 +452,53 @@ struct NodeParams {
     double uin_x, uin_y;     // inlet velocity
 };
 
+// Inlet rule, mask, body velocity, Eqs. 8-9 and 17-18, and the collision at node (x, y), in place
+// on the pulled populations f.  Returns the moments and sets id to the node's body id.
+template <typename T>
+__device__ __forceinline__ Macro<T> relax_node(T f[9], const uint8_t *__restrict__ mask,
+                                               const BodyState *__restrict__ bodies, const Geom &g,
+                                               const NodeParams &p, int x, int y, int &id)
+{
+    if (g.inlet && x == 0) zou_he_west(f, T(p.uin_x), T(p.uin_y));
+    id = *at(mask, unsigned(y * g.pitch + x));
+    T usx = T(0), usy = T(0);
+    if (id) solid_velocity(bodies[id - 1], x, y, usx, usy);
+    const Macro<T> m = moments(f, id != 0, usx, usy, T(p.k_relax), T(p.c_pen));
+    if (id) collide<true>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));   // penalized: forced
+    else collide<false>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));     // fluid: no force
+    return m;
+}
+
+// Store the nine post-collision populations of the node with lattice index `node` (row * pitch +
+// column) at element i of the planes dst, plane elements apart (the population planes in global
+// memory, or a workgroup's tile in LDS).  The stochastic formats draw their bits from (node, step),
+// so a value rounds the same wherever it is stored.
+template <int S, bool NT = false>
+__device__ __forceinline__ void store_node(typename Codec<S>::elem *__restrict__ dst, unsigned plane,
+                                           unsigned i, const typename Codec<S>::real f[9],
+                                           unsigned node, unsigned step)
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    if constexpr (C::stochastic) {
+        // one hash per node and step, then two 16-bit words per xorshift state
+        unsigned r = mix32(node ^ mix32(step * 0x9e3779b9u + 0x7f4a7c15u));
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            if (k % 2 == 0 && k > 0) r = xorshift32(r);
+            const unsigned bits = (k % 2) ? (r >> 16) : r;
+            if (NT) C::store_sr_nt(dst + k * plane, i, f[k], bits);
+            else C::store_sr(dst + k * plane, i, f[k], bits);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            if (NT) C::store_nt(dst + k * plane, i, f[k], weight<T>(k));
+            else C::store(dst + k * plane, i, f[k], weight<T>(k));
+        }
+    }
+}
+
 // The whole step at node (x, y): pull, edges, moments and penalization, collision, store.
 // Returns the moments (density, penalization force) for the reductions and the body id.
 template <int S, bool NT = false>
@@ -420,36 +507,12 @@ update_node(const typename Codec<S>::elem *__restrict__ src, typename Codec<S>::
             const uint8_t *__restrict__ mask, const BodyState *__restrict__ bodies, const Geom &g,
             const Outlet &o, const NodeParams &p, int x, int y, int &id, unsigned step)
 {
-    using C = Codec<S>;
-    using T = typename C::real;
+    using T = typename Codec<S>::real;
     T f[9];                  // shifted populations h = f - w
     pull<S>(src, x, y, g, o, f);
-    if (g.inlet && x == 0) zou_he_west(f, T(p.uin_x), T(p.uin_y));
+    const Macro<T> m = relax_node(f, mask, bodies, g, p, x, y, id);
     const unsigned i = y * g.pitch + x;
-    id = *at(mask, i);
-    T usx = T(0), usy = T(0);
-    if (id) solid_velocity(bodies[id - 1], x, y, usx, usy);
-    const Macro<T> m = moments(f, id != 0, usx, usy, T(p.k_relax), T(p.c_pen));
-    if (id) collide<true>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));   // penalized: forced
-    else collide<false>(f, m, T(p.sp), T(p.sm), T(p.kp), T(p.km));     // fluid: no force
-
-    if constexpr (C::stochastic) {
-        // one hash per node and step, then two 16-bit words per xorshift state
-        unsigned r = mix32(i ^ mix32(step * 0x9e3779b9u + 0x7f4a7c15u));
-#pragma unroll
-        for (int k = 0; k < 9; k++) {
-            if (k % 2 == 0 && k > 0) r = xorshift32(r);
-            const unsigned bits = (k % 2) ? (r >> 16) : r;
-            if (NT) C::store_sr_nt(dst + k * g.plane, i, f[k], bits);
-            else C::store_sr(dst + k * g.plane, i, f[k], bits);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; k++) {
-            if (NT) C::store_nt(dst + k * g.plane, i, f[k], weight<T>(k));
-            else C::store(dst + k * g.plane, i, f[k], weight<T>(k));
-        }
-    }
+    store_node<S, NT>(dst, g.plane, i, f, i, step);
     return m;
 }
 

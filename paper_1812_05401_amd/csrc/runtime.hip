@@ -52,9 +52,10 @@ void host_log(const char *fmt, ...)
     fprintf(stderr, "[vplbm] %s\n", buf);
 }
 
-static_assert(kF64 == VPLBM_F64 && kF32 == VPLBM_F32 && kF16S == VPLBM_F16S &&
-                  kBF16S == VPLBM_BF16S && kF32D == VPLBM_F32D && kF16SR == VPLBM_F16SR &&
-                  kBF16SR == VPLBM_BF16SR,
+static_assert(int(kF64) == int(VPLBM_F64) && int(kF32) == int(VPLBM_F32) &&
+                  int(kF16S) == int(VPLBM_F16S) && int(kBF16S) == int(VPLBM_BF16S) &&
+                  int(kF32D) == int(VPLBM_F32D) && int(kF16SR) == int(VPLBM_F16SR) &&
+                  int(kBF16SR) == int(VPLBM_BF16SR),
               "device storage ids follow the ABI");
 
 int elem_bytes(int storage)
@@ -80,7 +81,7 @@ int graph_chunk()
     int k = 32;
     if (const char *e = getenv("VPLBM_GRAPH_STEPS")) k = atoi(e);
     if (k < 0) k = 0;
-    return k & ~1;   // even, so a replay leaves the buffer parity unchanged
+    return k & ~1;   // even: a replay is whole two-step launches where those apply
 }
 
 }  // namespace
@@ -102,7 +103,7 @@ struct vplbm_sim_s {
     bool moving = false;
     int env_box[kMaxBodies][4];          // x0, y0, w, h swept by each moving body
     double *ring = nullptr;
-    double *acc = nullptr;               // [2][kSub][kRingWidth] reduction sub-slots
+    double *acc = nullptr;               // [kAccSets][kSub][kRingWidth] reduction sub-slots
     int ring_len = 0;
     unsigned *status = nullptr;
     long long *t_dev = nullptr;
@@ -113,7 +114,9 @@ struct vplbm_sim_s {
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_flip[2] = {0, 0};          // 1: a replay moves the state to the other buffer
     int graph_k = 0;
+    bool two_step = true;                // two steps per launch where the case allows it
     int64_t steps = 0;
     bool unstable = false;
     NodeParams params{};
@@ -191,16 +194,37 @@ hipError_t reset_outlet(vplbm_sim s)
     return launch_outlet_init(s->storage, step_args(s, s->cur, 0), s->outlet[s->cur], s->stream);
 }
 
-hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st)
+// Two steps per launch need a mask that stays the same over both steps and an outlet whose state
+// the intermediate step need not record.
+bool two_step_ok(vplbm_sim s)
 {
-    for (int j = 0; j < n; j++) {
-        if (s->moving) {
-            hipError_t e = place_bodies(s, j, st);
-            if (e != hipSuccess) return e;
+    return s->two_step && !s->moving && !s->outlet[0];
+}
+
+// Enqueue n steps starting from the state in buf[first_src]: pairs of steps in two-step launches
+// where allowed, else (and for an odd last step) one step per launch.  Every launch moves the state
+// to the other buffer; *flip is the parity of the number of launches.
+hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st, int *flip)
+{
+    const bool two = two_step_ok(s);
+    int src = first_src, j = 0;
+    while (j < n) {
+        hipError_t e;
+        if (two && n - j >= 2) {
+            e = launch_step2(s->storage, step_args(s, src, j), st);
+            j += 2;
+        } else {
+            if (s->moving) {
+                e = place_bodies(s, j, st);
+                if (e != hipSuccess) return e;
+            }
+            e = launch_step(s->storage, step_args(s, src, j), st);
+            j += 1;
         }
-        hipError_t e = launch_step(s->storage, step_args(s, (first_src + j) & 1, j), st);
         if (e != hipSuccess) return e;
+        src ^= 1;
     }
+    *flip = src ^ first_src;
     return launch_advance(s->t_dev, n, st);
 }
 
@@ -210,7 +234,7 @@ int ensure_graph(vplbm_sim s, int parity)
     if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_steps(s, parity, s->graph_k, s->cap_stream);
+    hipError_t e = enqueue_steps(s, parity, s->graph_k, s->cap_stream, &s->graph_flip[parity]);
     hipError_t e2 = hipStreamEndCapture(s->cap_stream, &graph);
     if (e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -375,13 +399,14 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     // faster there; inside the cache normal stores keep the next step's reads on chip).
     s->nt_store = 2 * s->buf_bytes > ((size_t)192 << 20) ? 1 : 0;
     if (const char *e = getenv("VPLBM_NT_STORE")) s->nt_store = atoi(e) ? 1 : 0;
+    if (const char *e = getenv("VPLBM_TWO_STEP")) s->two_step = atoi(e) != 0;   // 0: one step per launch
     struct { void **p; size_t n; } allocs[] = {
         {&s->buf[0], s->buf_bytes}, {&s->buf[1], s->buf_bytes},
         {(void **)&s->mask, (size_t)g.pitch * g.ny},
         {(void **)&s->d_params, sizeof(BodyParams) * kMaxBodies},
         {(void **)&s->d_state, sizeof(BodyState) * kMaxBodies},
         {(void **)&s->ring, sizeof(double) * kRingWidth * s->ring_len},
-        {(void **)&s->acc, sizeof(double) * 2 * kSub * kRingWidth},
+        {(void **)&s->acc, sizeof(double) * kAccSets * kSub * kRingWidth},
         {(void **)&s->status, sizeof(unsigned) * 4},
         {(void **)&s->t_dev, sizeof(long long)},
         {&s->outlet[0], cfg->bc_xhi == VPLBM_CONVECTIVE ? sizeof(double) * 3 * g.ny : 0},
@@ -400,7 +425,7 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     if (e == hipSuccess) e = hipMemsetAsync(s->d_state, 0, sizeof(BodyState) * kMaxBodies, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_params, 0, sizeof(BodyParams) * kMaxBodies, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->ring, 0, sizeof(double) * kRingWidth * s->ring_len, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->acc, 0, sizeof(double) * 2 * kSub * kRingWidth, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->acc, 0, sizeof(double) * kAccSets * kSub * kRingWidth, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->status, 0, sizeof(unsigned) * 4, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->t_dev, 0, sizeof(long long), s->stream);
     // Padding columns and the planes' tails are never read for results; clear them once.
@@ -416,8 +441,8 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     track(s, true);
     *out = s;
     host_log("create %p: %dx%d storage %d collision %d, tiles %dx%d x %d rows, %d planes of %d elements, "
-        "non-temporal stores %d", (void *)s, g.nx, g.ny, s->storage, cfg->collision,
-        1 << s->ts.bx_log2, s->ts.by, s->ts.rows, 9, g.plane, s->nt_store);
+        "non-temporal stores %d, two steps per launch %d", (void *)s, g.nx, g.ny, s->storage, cfg->collision,
+        1 << s->ts.bx_log2, s->ts.by, s->ts.rows, 9, g.plane, s->nt_store, two_step_ok(s) ? 1 : 0);
     return VPLBM_OK;
 }
 
@@ -480,6 +505,8 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
     s->nbodies = nbodies;
     s->moving = moving;
     s->device_mask = body_id == nullptr;
+    host_log("set_mask %p: %d bodies, moving %d, two steps per launch %d", (void *)s, nbodies,
+             moving ? 1 : 0, two_step_ok(s) ? 1 : 0);
     if (nbodies) HIP_TRY(hipMemcpyAsync(s->d_params, s->h_params, sizeof(BodyParams) * nbodies, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_bodies(s->d_params, s->d_state, nbodies, s->t_dev, 0, s->stream));
     if (body_id) {
@@ -506,11 +533,13 @@ int vplbm_step(vplbm_sim s, int64_t nsteps)
         HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
         s->steps += s->graph_k;
         nsteps -= s->graph_k;
+        s->cur ^= s->graph_flip[s->cur];
     }
     if (nsteps > 0) {
-        HIP_TRY(enqueue_steps(s, s->cur, (int)nsteps, s->stream));
+        int flip = 0;
+        HIP_TRY(enqueue_steps(s, s->cur, (int)nsteps, s->stream, &flip));
         s->steps += nsteps;
-        s->cur ^= (int)(nsteps & 1);
+        s->cur ^= flip;
     }
     return VPLBM_OK;
 }
@@ -595,7 +624,7 @@ int vplbm_set_populations(vplbm_sim s, const double *pop, int64_t step)
     HIP_TRY(reset_outlet(s));
     long long t = step;
     HIP_TRY(hipMemcpyAsync(s->t_dev, &t, sizeof t, hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(launch_fill_f64(s->acc, (size_t)2 * kSub * kRingWidth, 0.0, s->stream));
+    HIP_TRY(launch_fill_f64(s->acc, (size_t)kAccSets * kSub * kRingWidth, 0.0, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     s->steps = step;
     return VPLBM_OK;

@@ -1,0 +1,141 @@
+"""Two steps per launch (the intermediate step kept in LDS) against one step per launch.  The
+populations must be bitwise the same in every storage format and edge combination, over graph
+replays, odd remainders and restarts.  The per-step ring values (mass, body forces) are FP64 sums
+over different tilings, so they agree up to summation order (1e-13 relative)."""
+import contextlib
+import os
+
+import numpy as np
+import pytest
+
+from paper_1812_05401_amd import inputs as I
+from tests.helpers import gpu_sim
+from tests.test_gpu_parity import CASES, build_case
+
+pytestmark = pytest.mark.gpu
+
+STORAGES = ["f64", "f32", "f32d", "f16s", "bf16s", "f16sr", "bf16sr"]
+# static masks without a convective outlet: the cases the two-step kernel takes
+STATIC = [c for c in CASES if not c[10] and c[7] != I.CHANNEL_CONVECTIVE]
+OTHER = [c for c in CASES if c[10] or c[7] == I.CHANNEL_CONVECTIVE]
+
+
+@contextlib.contextmanager
+def env(**kw):
+    old = {k: os.environ.get(k) for k in kw}
+    os.environ.update({k: str(v) for k, v in kw.items()})
+    try:
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def make(case, ids, storage, fields, two_step, capfd=None):
+    with env(VPLBM_TWO_STEP=int(two_step), VPLBM_LOG=1):
+        s = gpu_sim(case, storage=storage, device_mask=ids is None)
+        if ids is not None:
+            s.set_mask(ids, case.bodies)
+    if capfd is not None:
+        assert last_report(capfd) == int(two_step)
+    s.init_fields(*fields)
+    return s
+
+
+def last_report(capfd):
+    """The last 'two steps per launch' flag the library logged (at create or set_mask)."""
+    err = capfd.readouterr().err
+    flags = [int(l.rsplit(" ", 1)[1]) for l in err.splitlines() if "two steps per launch" in l]
+    assert flags, err[-400:]
+    return flags[-1]
+
+
+def same_run(a, b, first, count, what):
+    pa, pb = a.populations(), b.populations()
+    assert np.array_equal(pa, pb), f"{what}: populations differ at {np.argwhere(pa != pb)[:3]}"
+    sa, sb = a.force_series(first, count), b.force_series(first, count)
+    scale = np.maximum(np.max(np.abs(sb), axis=0), 1e-300)
+    d = np.max(np.abs(sa - sb) / scale)
+    assert d <= 1e-13, f"{what}: ring values differ by {d:.2e}"
+    oa, ob = a.observables(), b.observables()
+    assert oa["step"] == ob["step"] and oa["status"] == ob["status"] == 0
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("spec", STATIC, ids=[c[0] for c in STATIC])
+def test_two_step_bitwise_equals_one_step(gpu, capfd, spec, storage):
+    """101 steps (three 32-step graph replays, two two-step launches and a one-step launch), then
+    1 and 3 more: bitwise the same populations as one step per launch."""
+    case, ids = build_case(*spec, seed=11)
+    fields = I.random_fields(case.nx, case.ny, 11, u_mean=case.u_in)
+    a = make(case, ids, storage, fields, True, capfd)
+    b = make(case, ids, storage, fields, False, capfd)
+    done = 0
+    for n in (101, 1, 3):
+        a.step(n)
+        b.step(n)
+        done += n
+        same_run(a, b, 0, done, f"{spec[0]}/{storage} after {done} steps")
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("spec", OTHER, ids=[c[0] for c in OTHER])
+def test_moving_bodies_and_convective_outlet_take_one_step_per_launch(gpu, capfd, spec):
+    """A mask rebuilt every step or a convective outlet keeps one step per launch."""
+    case, ids = build_case(*spec, seed=3)
+    with env(VPLBM_LOG=1):
+        s = gpu_sim(case, storage="f32", device_mask=ids is None)
+        if ids is not None:
+            s.set_mask(ids, case.bodies)
+    assert last_report(capfd) == 0
+    s.close()
+
+
+def test_two_step_ring_and_restart(gpu):
+    """Mixed call sizes with observations in between (each observation folds the last two steps),
+    then a restart from populations at an odd step: ring entries and populations match the
+    one-step path."""
+    spec = CASES[2]                                           # channel with two disks
+    case, ids = build_case(*spec, seed=21)
+    fields = I.random_fields(case.nx, case.ny, 21, u_mean=case.u_in)
+    a = make(case, ids, "f64", fields, True)
+    b = make(case, ids, "f64", fields, False)
+    done = 0
+    for n in (2, 1, 2, 64, 5, 33, 4):
+        a.step(n)
+        b.step(n)
+        done += n
+        assert a.observables()["mass"] == pytest.approx(b.observables()["mass"], rel=1e-14)
+    same_run(a, b, 0, done, "mixed calls")
+    pop = b.populations()
+    t0 = 1001
+    a.set_populations(pop, t0)
+    b.set_populations(pop, t0)
+    a.step(37)
+    b.step(37)
+    same_run(a, b, t0, 37, "after a restart at an odd step")
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("nx,ny,storage,steps", [
+    (2048, 512, "f32", 200),
+    (8192, 2048, "f16s", 64),
+    (8192, 2048, "f32", 64),
+], ids=["wake_2048x512_f32", "wake_8192x2048_f16s", "wake_8192x2048_f32"])
+def test_two_step_full_size(gpu, nx, ny, storage, steps):
+    """The benchmark lattices in the launch configuration the benchmark times (graph replays of
+    two-step launches, non-temporal stores on the large lattice)."""
+    case = I.cylinder_wake(nx, ny, storage=storage)
+    fields = I.random_fields(case.nx, case.ny, 4, u_mean=case.u_in)
+    a = make(case, None, storage, fields, True)
+    b = make(case, None, storage, fields, False)
+    a.step(steps)
+    b.step(steps)
+    same_run(a, b, 0, steps, f"{case.name}/{storage}")
+    a.close()
+    b.close()
