@@ -145,20 +145,17 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 // planes instead of two of each.  The halo is computed twice (by this tile and its neighbour):
 // (TW + 2)(TH + 2) / (TW TH) of the nodes in phase 1.  Static masks only (bodies at rest or
 // spinning in place), and no convective outlet: the host falls back to one step per launch.
-template <int S> struct Tile2 {
-    static constexpr int w = 128, h = 8;       // 4-byte and 2-byte storage: 46.8 / 23.4 KB of LDS
-};
-template <> struct Tile2<kF64> {
-    static constexpr int w = 64, h = 8;        // 8-byte storage: 47.5 KB of LDS
-};
-
-template <int S, bool NT>
+// Tiles (measured): 128 x 8 for 4-byte storage (47 KB of LDS, three workgroups per CU), 64 x 8
+// for 8-byte storage (48 KB); for 2-byte storage 128 x 16 on large lattices (42 KB: less halo,
+// 10-13% faster at 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill
+// the chip.
+template <int S, int TW, int TH, bool NT>
 __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
 {
     using C = Codec<S>;
     using T = typename C::real;
     using E = typename C::elem;
-    constexpr int TW = Tile2<S>::w, TH = Tile2<S>::h, EW = TW + 2, EN = EW * (TH + 2);
+    constexpr int EW = TW + 2, EN = EW * (TH + 2);
     constexpr int NW = kBlock2 / 64;
     static_assert((TW * TH) % kBlock2 == 0, "phase 2 gives every thread the same number of nodes");
     __shared__ E mid[9 * EN];                      // step t on the tile and its halo
@@ -313,29 +310,25 @@ hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-// Tiles of the two-step kernel along x and y.
-static void tiles2(int storage, const Geom &g, int &ntx, int &nty)
+template <int S, int TW, int TH>
+static void launch2(const StepArgs &a, hipStream_t st)
 {
-    const int tw = storage == kF64 ? Tile2<kF64>::w : Tile2<kF32>::w;
-    const int th = storage == kF64 ? Tile2<kF64>::h : Tile2<kF32>::h;
-    ntx = (g.nx + tw - 1) / tw;
-    nty = (g.ny + th - 1) / th;
+    const dim3 grid(((a.g.nx + TW - 1) / TW) * ((a.g.ny + TH - 1) / TH)), block(kBlock2);
+    if (a.nt_store) step2_kernel<S, TW, TH, true><<<grid, block, 0, st>>>(a);
+    else step2_kernel<S, TW, TH, false><<<grid, block, 0, st>>>(a);
 }
 
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st)
 {
-    int ntx, nty;
-    tiles2(storage, a.g, ntx, nty);
-    const dim3 grid(ntx * nty), block(kBlock2);
-#define VPLBM_STEP2(S)                                                                            \
-    (a.nt_store ? step2_kernel<S, true><<<grid, block, 0, st>>>(a)                                  \
-                : step2_kernel<S, false><<<grid, block, 0, st>>>(a))
+    // 2-byte storage: tall tiles once there are enough of them (4 M nodes and up)
+    const bool tall = (long long)((a.g.nx + 127) / 128) * ((a.g.ny + 15) / 16) >= 2048;
+#define VPLBM_STEP2(S) (tall ? launch2<S, 128, 16>(a, st) : launch2<S, 128, 8>(a, st))
     switch (storage) {
-    case kF64: VPLBM_STEP2(kF64); break;
-    case kF32: VPLBM_STEP2(kF32); break;
+    case kF64: launch2<kF64, 64, 8>(a, st); break;
+    case kF32: launch2<kF32, 128, 8>(a, st); break;
+    case kF32D: launch2<kF32D, 128, 8>(a, st); break;
     case kF16S: VPLBM_STEP2(kF16S); break;
     case kBF16S: VPLBM_STEP2(kBF16S); break;
-    case kF32D: VPLBM_STEP2(kF32D); break;
     case kF16SR: VPLBM_STEP2(kF16SR); break;
     case kBF16SR: VPLBM_STEP2(kBF16SR); break;
     default: return hipErrorInvalidValue;

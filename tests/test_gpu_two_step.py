@@ -126,10 +126,12 @@ def test_two_step_ring_and_restart(gpu):
     (2048, 512, "f32", 200),
     (8192, 2048, "f16s", 64),
     (8192, 2048, "f32", 64),
-], ids=["wake_2048x512_f32", "wake_8192x2048_f16s", "wake_8192x2048_f32"])
+    (2100, 2001, "bf16sr", 21),
+], ids=["wake_2048x512_f32", "wake_8192x2048_f16s", "wake_8192x2048_f32", "ragged_tall_tiles_bf16sr"])
 def test_two_step_full_size(gpu, nx, ny, storage, steps):
     """The benchmark lattices in the launch configuration the benchmark times (graph replays of
-    two-step launches, non-temporal stores on the large lattice)."""
+    two-step launches, non-temporal stores on the large lattice), and a ragged lattice large
+    enough for the tall 2-byte tiles."""
     case = I.cylinder_wake(nx, ny, storage=storage)
     fields = I.random_fields(case.nx, case.ny, 4, u_mean=case.u_in)
     a = make(case, None, storage, fields, True)
