@@ -5,10 +5,12 @@
 A "step" is one lattice update of the whole grid: pull-streaming, edge rules, mask fetch,
 moments, penalization, collision, store, and the FP64 mass/force reductions.  The default
 workload is the 2048 x 512 cylinder wake (VP-MRT, FP32 storage, Zou-He inlet, outflow, free-slip
-walls, disk D = 64, Re = 200).  Its two population buffers (75 MB) fit in the 256 MB Infinity
-Cache, so the line also carries `hbm_resident`: the 8192 x 2048 oscillating-cylinder workload
-(FP32, mask rebuilt every step), whose buffers (1.2 GB) do not, and `reduced_precision`: the
-8192 x 2048 cylinder in FP16/BF16 storage shifted by the lattice weights.
+walls, disk D = 64, Re = 200).  Its mask is static, so the library runs two steps per launch
+(the intermediate step kept in LDS); `one_step_per_launch` times the same workload with one step
+per launch, the memory-bound kernel.  The two population buffers (75 MB) fit in the 256 MB
+Infinity Cache, so the line also carries `hbm_resident`: the 8192 x 2048 oscillating-cylinder
+workload (FP32, mask rebuilt every step, so one step per launch), whose buffers (1.2 GB) do not,
+and `reduced_precision`: the 8192 x 2048 cylinder in every storage format.
 
 Prints one JSON line.  Inputs are synthetic (seeded geometry, uniform start) and resident on the
 GPU before timing starts.  `--copy-probe BYTES` instead times a plain device copy (the measured
@@ -26,6 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM roofline (D2Q9 VP-MRT step); served p50/p99 time-to-result"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E datasheet peak
+# VALU issue rate without packed FP32 (which the build disables): 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz lane-instructions per second (FP32 FMA at this rate is the datasheet's 157.3 TFLOP/s
+# halved for packing and halved again for counting an FMA as two flops).
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def source_digest():
@@ -36,21 +42,30 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, storage):
-    """HBM bytes per step-kernel launch from the committed counter summary, if it was taken on
-    the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def profile_entry(table, workload, storage, steps_per_launch):
+    """An entry of a committed counter summary (profiles/<table>.json) for this workload and
+    kernel, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{table}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         tab = json.load(f)
-    ent = tab.get(f"{workload}/{storage}")
+    ent = tab.get(f"{workload}/{storage}/{steps_per_launch}")
     if not ent or ent.get("source_digest") != source_digest():
         return None
-    return ent.get("bytes_per_launch")
+    return ent
 
 
-def time_workload(case, steps, warmup, storage=None):
+def measured_traffic(workload, storage, steps_per_launch=1):
+    """HBM bytes per step-kernel launch from the committed FETCH_SIZE/WRITE_SIZE summary."""
+    ent = profile_entry("traffic", workload, storage, steps_per_launch)
+    return ent and ent.get("bytes_per_launch")
+
+
+def time_workload(case, steps, warmup, storage=None, two_step=True):
+    """Time `steps` steps of `case` after `warmup`.  two_step=False creates the simulation with
+    one step per launch (VPLBM_TWO_STEP=0); otherwise the library takes two steps per launch where
+    the case allows it."""
     import torch
     from paper_1812_05401_amd import binding as B
     if storage:
@@ -60,8 +75,17 @@ def time_workload(case, steps, warmup, storage=None):
     # reads as "use a stream of your own").
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    sim = B.Simulation(case, stream=int(stream.cuda_stream))
+    old = os.environ.get("VPLBM_TWO_STEP")
+    os.environ["VPLBM_TWO_STEP"] = "1" if two_step else "0"
+    try:
+        sim = B.Simulation(case, stream=int(stream.cuda_stream))
+    finally:
+        if old is None:
+            os.environ.pop("VPLBM_TWO_STEP")
+        else:
+            os.environ["VPLBM_TWO_STEP"] = old
     assert sim.stream == stream.cuda_stream
+    spl = sim.steps_per_launch
     sim.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -78,18 +102,40 @@ def time_workload(case, steps, warmup, storage=None):
     if obs["status"] != 0:
         raise RuntimeError(f"{case.name}: unstable")
     bpu = B.vplbm_bytes_per_update(case.storage)
-    per_step_s = gpu_ms / 1e3 / steps
-    achieved = bpu * case.nodes / per_step_s / 1e9
-    traffic = measured_traffic(case.name, case.storage)
+    # One launch updates every node spl times (the graph's step-counter kernel, one per 32 steps,
+    # is noise).  Its algorithmic bytes are one read and one write of the planes plus the mask
+    # whatever spl is: the two-step kernel keeps the intermediate step on chip.
+    launch_s = gpu_ms / 1e3 / steps * spl
+    bytes_launch = bpu * case.nodes
+    hbm = bytes_launch / launch_s / 1e9
+    kernel = "vplbm::step2_kernel" if spl == 2 else "vplbm::step_kernel"
+    roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(case.name, case.storage, spl),
+            "kernel": kernel, "lattice_updates_per_launch": spl, "launch_us": round(launch_s * 1e6, 3),
+            "bytes_per_launch": bytes_launch, "bytes_per_node_per_launch": bpu}
+    valu = profile_entry("valu", case.name, case.storage, spl)
+    if spl == 2 and valu:
+        # The two-step kernel moves half the bytes per update and is bound by the vector ALUs:
+        # report it against their issue rate, with its VALU instructions (SQ_INSTS_VALU x 64
+        # lanes per launch, from the committed counter summary), and keep the HBM figures beside.
+        t = valu["valu_lane_instr_per_launch"] / launch_s / 1e12
+        roof = {"bound": "alu", "achieved": round(t, 3), "peak": round(VALU_PEAK_T, 3),
+                "unit": "T VALU lane-instructions/s", "frac": round(t / VALU_PEAK_T, 4),
+                "traffic": roof["traffic"], "kernel": kernel,
+                "lattice_updates_per_launch": spl, "launch_us": roof["launch_us"],
+                "valu_lane_instr_per_launch": valu["valu_lane_instr_per_launch"],
+                "valu_per_lattice_update": round(valu["valu_lane_instr_per_launch"] / (spl * case.nodes), 1),
+                "hbm": {"achieved": roof["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": roof["frac"], "bytes_per_launch": bytes_launch}}
     return {
         "workload": case.name, "nx": case.nx, "ny": case.ny, "storage": case.storage,
-        "collision": case.collision, "steps": steps,
+        "collision": case.collision, "steps": steps, "steps_per_launch": spl,
         "mlups": case.nodes * steps / (gpu_ms / 1e3) / 1e6,
         "ms_per_step": gpu_ms / steps, "wall_s": wall, "mass": obs["mass"],
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_update": bpu,
-                     "kernel": "vplbm::step_kernel"},
+        # what one step per launch would have to move at this rate (not a measured bandwidth)
+        "one_step_equivalent_gbs": round(bpu * case.nodes * steps / (gpu_ms / 1e3) / 1e9, 1),
+        "roofline": roof,
     }
 
 
@@ -292,7 +338,15 @@ def main():
                    "bodies": len(case.bodies), "reductions": "fp64 mass + body force, every step",
                    "cache_resident": case.nx * case.ny * 2 * 9 * {"f64": 8, "f32": 4}.get(case.storage, 2) < 256e6},
         "roofline": main_res["roofline"],
+        "steps_per_launch": main_res["steps_per_launch"],
+        "one_step_equivalent_gbs": main_res["one_step_equivalent_gbs"],
     }
+    if main_res["steps_per_launch"] == 2:
+        # the same workload with one step per launch: the memory-bound kernel and its roofline
+        one = time_workload(workloads[args.workload](), args.steps, args.warmup,
+                            storage=args.storage or None, two_step=False)
+        line["one_step_per_launch"] = {k: one[k] for k in ("mlups", "ms_per_step", "roofline")}
+        print(f"# {case.name} one step per launch: {one['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     if not args.no_extra:
         big = I.oscillating_cylinder_8192x2048()
         r = time_workload(big, 400, 40)
@@ -302,7 +356,7 @@ def main():
         for st in ("f64", "f32", "f32d", "f16s", "f16sr", "bf16s", "bf16sr"):
             c = I.cylinder_wake_8192x2048(st)
             r = time_workload(c, 400, 40)
-            red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "roofline")}
+            red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "steps_per_launch", "roofline")}
             print(f"# {c.name}/{st}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         line["reduced_precision"] = {"workload": "cylinder_wake_8192x2048", **red}
         # FP32 square channels from cache-resident to far beyond the 256 MB Infinity Cache
@@ -312,13 +366,18 @@ def main():
             r = time_workload(c, steps, 20)
             sweep.append({"grid": f"{n}x{n}", "buffers_bytes": 2 * 9 * 4 * n * n,
                           "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
-                          "frac": r["roofline"]["frac"]})
+                          "steps_per_launch": r["steps_per_launch"],
+                          "one_step_equivalent_gbs": r["one_step_equivalent_gbs"]})
             print(f"# square {n}x{n}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         line["square_sweep_f32"] = sweep
         cp = measure_copy(1 << 30, 20)
         line["copy_probe"] = cp
-        for obj in [line["roofline"], line["hbm_resident"]["roofline"]]:
-            obj["frac_of_copy"] = round(obj["achieved"] / cp["gbs_read_plus_write"], 4)
+        for obj in [line["roofline"], line["hbm_resident"]["roofline"],
+                    line.get("one_step_per_launch", {}).get("roofline")]:
+            if not obj:
+                continue
+            h = obj if obj["bound"] == "hbm" else obj["hbm"]
+            h["frac_of_copy"] = round(h["achieved"] / cp["gbs_read_plus_write"], 4)
     if not args.no_serving:
         line["serving"] = serving_leg(args.serving_requests, (0.7, 1.2), 2 << 30, (0.7, 1.2))
     if not args.no_cpu_baseline:

@@ -81,6 +81,7 @@ SIGNATURES = [
     ("vplbm_momentum_exchange", C.c_int, [C.c_void_p, _dp, _dp]),
     ("vplbm_residual", C.c_int, [C.c_void_p, _dp]),
     ("vplbm_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("vplbm_steps_per_launch", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     ("vplbm_stream", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     ("vplbm_bytes_per_update", C.c_int, [C.c_int32, C.POINTER(C.c_int64)]),
     ("vplbm_pool_create", C.c_int, [C.POINTER(PoolConfig), C.POINTER(C.c_void_p)]),
@@ -250,6 +251,12 @@ def vplbm_residual(h):
     return r.value
 
 
+def vplbm_steps_per_launch(h):
+    n = C.c_int32()
+    check(load().vplbm_steps_per_launch(h, C.byref(n)))
+    return n.value
+
+
 def vplbm_steps_done(h):
     n = C.c_int64()
     check(load().vplbm_steps_done(h, C.byref(n)))
@@ -336,6 +343,11 @@ class Simulation:
     @property
     def steps_done(self):
         return vplbm_steps_done(self.h)
+
+    @property
+    def steps_per_launch(self):
+        """2 when pairs of steps share a launch (static mask, no convective outlet), else 1."""
+        return vplbm_steps_per_launch(self.h)
 
     @property
     def stream(self):

@@ -704,6 +704,13 @@ int vplbm_residual(vplbm_sim s, double *residual)
     return VPLBM_OK;
 }
 
+int vplbm_steps_per_launch(vplbm_sim s, int32_t *steps)
+{
+    if (!valid(s) || !steps) return fail(VPLBM_EINVAL, "invalid handle or NULL output");
+    *steps = two_step_ok(s) ? 2 : 1;
+    return VPLBM_OK;
+}
+
 int vplbm_steps_done(vplbm_sim s, int64_t *steps)
 {
     if (!valid(s) || !steps) return fail(VPLBM_EINVAL, "invalid handle or NULL output");

@@ -95,6 +95,8 @@ def test_null_and_foreign_handles_are_rejected():
     assert lib.vplbm_set_mask(bogus, None, None, 0) == B.EINVAL
     assert lib.vplbm_destroy(bogus) == B.EINVAL
     assert lib.vplbm_steps_done(bogus, C.byref(n)) == B.EINVAL
+    k = C.c_int32()
+    assert lib.vplbm_steps_per_launch(bogus, C.byref(k)) == B.EINVAL
     assert lib.vplbm_stream(bogus, C.byref(s)) == B.EINVAL
     assert lib.vplbm_get_populations(bogus, None) == B.EINVAL
     assert lib.vplbm_force_series(bogus, 0, 1, None) == B.EINVAL
