@@ -28,10 +28,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM roofline (D2Q9 VP-MRT step); served p50/p99 time-to-result"
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E datasheet peak
-# VALU issue rate without packed FP32 (which the build disables): 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz lane-instructions per second (FP32 FMA at this rate is the datasheet's 157.3 TFLOP/s
-# halved for packing and halved again for counting an FMA as two flops).
-VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 FMA issue rate without packed FP32 (which the build disables): 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz lane-instructions per second (the datasheet's 157.3 TFLOP/s halved for packing and
+# halved again for counting an FMA as two flops).  Independent FMA chains reach 35.6 T/s of it;
+# some other instruction mixes issue faster, so a kernel's VALU rate against it is a diagnostic.
+VALU_FMA_RATE_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def source_digest():
@@ -115,19 +116,13 @@ def time_workload(case, steps, warmup, storage=None, two_step=True):
             "kernel": kernel, "lattice_updates_per_launch": spl, "launch_us": round(launch_s * 1e6, 3),
             "bytes_per_launch": bytes_launch, "bytes_per_node_per_launch": bpu}
     valu = profile_entry("valu", case.name, case.storage, spl)
-    if spl == 2 and valu:
-        # The two-step kernel moves half the bytes per update and is bound by the vector ALUs:
-        # report it against their issue rate, with its VALU instructions (SQ_INSTS_VALU x 64
-        # lanes per launch, from the committed counter summary), and keep the HBM figures beside.
+    if valu:
+        # The kernel's VALU instructions (SQ_INSTS_VALU x 64 lanes per launch, from the committed
+        # counter summary) over the same launch time: how busy the vector ALUs are beside HBM.
         t = valu["valu_lane_instr_per_launch"] / launch_s / 1e12
-        roof = {"bound": "alu", "achieved": round(t, 3), "peak": round(VALU_PEAK_T, 3),
-                "unit": "T VALU lane-instructions/s", "frac": round(t / VALU_PEAK_T, 4),
-                "traffic": roof["traffic"], "kernel": kernel,
-                "lattice_updates_per_launch": spl, "launch_us": roof["launch_us"],
-                "valu_lane_instr_per_launch": valu["valu_lane_instr_per_launch"],
-                "valu_per_lattice_update": round(valu["valu_lane_instr_per_launch"] / (spl * case.nodes), 1),
-                "hbm": {"achieved": roof["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": roof["frac"], "bytes_per_launch": bytes_launch}}
+        roof["valu"] = {"achieved": round(t, 3), "fma_issue_rate": round(VALU_FMA_RATE_T, 3),
+                        "unit": "T lane-instructions/s", "ratio": round(t / VALU_FMA_RATE_T, 4),
+                        "per_lattice_update": valu["valu_per_lattice_update"]}
     return {
         "workload": case.name, "nx": case.nx, "ny": case.ny, "storage": case.storage,
         "collision": case.collision, "steps": steps, "steps_per_launch": spl,
@@ -376,8 +371,7 @@ def main():
                     line.get("one_step_per_launch", {}).get("roofline")]:
             if not obj:
                 continue
-            h = obj if obj["bound"] == "hbm" else obj["hbm"]
-            h["frac_of_copy"] = round(h["achieved"] / cp["gbs_read_plus_write"], 4)
+            obj["frac_of_copy"] = round(obj["achieved"] / cp["gbs_read_plus_write"], 4)
     if not args.no_serving:
         line["serving"] = serving_leg(args.serving_requests, (0.7, 1.2), 2 << 30, (0.7, 1.2))
     if not args.no_cpu_baseline:
