@@ -143,8 +143,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 // of the tile from LDS and stores it.  Each node's arithmetic is the one-step kernel's, so the
 // populations are bitwise those of two one-step launches, with one read and one write of the
 // planes instead of two of each.  The halo is computed twice (by this tile and its neighbour):
-// (TW + 2)(TH + 2) / (TW TH) of the nodes in phase 1.  Static masks only (bodies at rest or
-// spinning in place), and no convective outlet: the host falls back to one step per launch.
+// (TW + 2)(TH + 2) / (TW TH) of the nodes in phase 1.  Phase 1 takes the mask and body states of
+// step t, phase 2 those of step t + 1 (where bodies move, the host rebuilds two masks).  No
+// convective outlet: the host falls back to one step per launch.
 // Tiles (measured): 128 x 8 for 4-byte storage (47 KB of LDS, three workgroups per CU), 64 x 8
 // for 8-byte storage (48 KB); for 2-byte storage 128 x 16 on large lattices (42 KB: less halo,
 // 10-13% faster at 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         if ((x < g.nx) & (y < g.ny)) {
             T f[9];
             pull_tile<S>(mid, EN, EW, x, y, x0, y0, g, f);
-            const Macro<T> m = relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
+            const Macro<T> m = relax_node(f, a.mask2, a.bodies2, g, a.p, x, y, id);
             const unsigned i = y * g.pitch + x;
             store_node<S, NT>(dst, g.plane, i, f, i, (unsigned)(t + 1));
             const double rho_d = 1.0 + double(m.drho);

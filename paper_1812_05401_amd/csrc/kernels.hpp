@@ -31,6 +31,8 @@ struct StepArgs {
     void *dst;               // planes this step writes
     const uint8_t *mask;     // body id per node (pitch = geometry pitch)
     const BodyState *bodies; // body state at this step's time
+    const uint8_t *mask2;    // two-step launches: mask and body states of the second step (the
+    const BodyState *bodies2;//   same arrays as mask / bodies unless bodies move)
     double *ring;            // [ring_len][kRingWidth] per-step observables
     double *acc;             // [kAccSets][kSub][kRingWidth] per-step partial sums
     unsigned *status;        // bit 0: non-finite or non-positive density seen
@@ -53,8 +55,8 @@ struct TileShape {
 TileShape tile_shape(int nx, int ny, int elem_bytes);
 
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st);
-// Steps *t_base + t_off and the one after in one launch, from a.src into a.dst (static mask, no
-// convective outlet).
+// Steps *t_base + t_off and the one after in one launch, from a.src into a.dst; the second step
+// takes its mask and body states from a.mask2 / a.bodies2 (no convective outlet).
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st);
 
 // Per-node density and penalized velocity of the current state into dense FP64 arrays.

@@ -97,6 +97,8 @@ struct vplbm_sim_s {
     uint8_t *mask = nullptr;
     BodyParams *d_params = nullptr;
     BodyState *d_state = nullptr;
+    uint8_t *mask_alt = nullptr;         // moving bodies: mask and body states of the first step of
+    BodyState *d_state_alt = nullptr;    //   a two-step launch (mask / d_state take the second)
     BodyParams h_params[kMaxBodies];
     int nbodies = 0;
     bool device_mask = false;
@@ -153,6 +155,8 @@ StepArgs step_args(vplbm_sim s, int src, int t_off)
     a.dst = s->buf[src ^ 1];
     a.mask = s->mask;
     a.bodies = s->d_state;
+    a.mask2 = s->mask;
+    a.bodies2 = s->d_state;
     a.ring = s->ring;
     a.acc = s->acc;
     a.status = s->status;
@@ -173,18 +177,24 @@ StepArgs step_args(vplbm_sim s, int src, int t_off)
     return a;
 }
 
-// Body states and the swept part of the mask for the step at *t_dev + t_off (moving bodies).
-hipError_t place_bodies(vplbm_sim s, int t_off, hipStream_t st)
+// Body states and the swept part of the mask for the step at *t_dev + t_off (moving bodies),
+// into `mask` / `state` (the simulation's own, or the second step's of a two-step launch).
+hipError_t place_bodies(vplbm_sim s, int t_off, hipStream_t st, uint8_t *mask, BodyState *state)
 {
-    hipError_t e = launch_bodies(s->d_params, s->d_state, s->nbodies, s->t_dev, t_off, st);
+    hipError_t e = launch_bodies(s->d_params, state, s->nbodies, s->t_dev, t_off, st);
     if (e != hipSuccess || !s->moving) return e;
     for (int k = 0; k < s->nbodies; k++) {
         const int *b = s->env_box[k];
         if (b[2] <= 0) continue;
-        e = launch_mask(s->mask, s->g, s->d_params, s->d_state, s->nbodies, b[0], b[1], b[2], b[3], st);
+        e = launch_mask(mask, s->g, s->d_params, state, s->nbodies, b[0], b[1], b[2], b[3], st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t place_bodies(vplbm_sim s, int t_off, hipStream_t st)
+{
+    return place_bodies(s, t_off, st, s->mask, s->d_state);
 }
 
 // Convective outlet: the previous-step outlet values start as the current state's last column.
@@ -194,11 +204,11 @@ hipError_t reset_outlet(vplbm_sim s)
     return launch_outlet_init(s->storage, step_args(s, s->cur, 0), s->outlet[s->cur], s->stream);
 }
 
-// Two steps per launch need a mask that stays the same over both steps and an outlet whose state
-// the intermediate step need not record.
+// Two steps per launch need an outlet whose state the intermediate step need not record; moving
+// bodies take a second mask for the first step.
 bool two_step_ok(vplbm_sim s)
 {
-    return s->two_step && !s->moving && !s->outlet[0];
+    return s->two_step && !s->outlet[0] && (!s->moving || s->mask_alt);
 }
 
 // Enqueue n steps starting from the state in buf[first_src]: pairs of steps in two-step launches
@@ -211,7 +221,17 @@ hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st, int 
     while (j < n) {
         hipError_t e;
         if (two && n - j >= 2) {
-            e = launch_step2(s->storage, step_args(s, src, j), st);
+            StepArgs a = step_args(s, src, j);
+            if (s->moving) {
+                // the first step on the other mask, the second on the simulation's own: after
+                // the launch it holds the last step's bodies, as after one step per launch
+                e = place_bodies(s, j, st, s->mask_alt, s->d_state_alt);
+                if (e == hipSuccess) e = place_bodies(s, j + 1, st);
+                if (e != hipSuccess) return e;
+                a.mask = s->mask_alt;
+                a.bodies = s->d_state_alt;
+            }
+            e = launch_step2(s->storage, a, st);
             j += 2;
         } else {
             if (s->moving) {
@@ -267,7 +287,7 @@ void release(vplbm_sim s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (int p = 0; p < 2; p++)
         if (s->graph[p]) (void)hipGraphExecDestroy(s->graph[p]);
-    void *ptrs[] = {s->buf[0], s->buf[1], s->mask, s->d_params, s->d_state, s->ring, s->acc,
+    void *ptrs[] = {s->buf[0], s->buf[1], s->mask, s->mask_alt, s->d_params, s->d_state, s->d_state_alt, s->ring, s->acc,
                     s->status, s->t_dev, s->staging, s->outlet[0], s->outlet[1], s->snap, s->rpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -405,6 +425,7 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
         {(void **)&s->mask, (size_t)g.pitch * g.ny},
         {(void **)&s->d_params, sizeof(BodyParams) * kMaxBodies},
         {(void **)&s->d_state, sizeof(BodyState) * kMaxBodies},
+        {(void **)&s->d_state_alt, sizeof(BodyState) * kMaxBodies},
         {(void **)&s->ring, sizeof(double) * kRingWidth * s->ring_len},
         {(void **)&s->acc, sizeof(double) * kAccSets * kSub * kRingWidth},
         {(void **)&s->status, sizeof(unsigned) * 4},
@@ -423,6 +444,7 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     }
     hipError_t e = hipMemsetAsync(s->mask, 0, (size_t)g.pitch * g.ny, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_state, 0, sizeof(BodyState) * kMaxBodies, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_state_alt, 0, sizeof(BodyState) * kMaxBodies, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_params, 0, sizeof(BodyParams) * kMaxBodies, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->ring, 0, sizeof(double) * kRingWidth * s->ring_len, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->acc, 0, sizeof(double) * kAccSets * kSub * kRingWidth, s->stream);
@@ -502,11 +524,15 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
             }
         }
     }
+    // Moving bodies: the first step of a two-step launch takes a mask of its own.
+    if (moving && !s->mask_alt && hipMalloc(&s->mask_alt, (size_t)g.pitch * g.ny) != hipSuccess) {
+        (void)hipGetLastError();
+        s->mask_alt = nullptr;
+        return fail(VPLBM_ENOMEM, "cannot allocate the second mask (%zu bytes)", (size_t)g.pitch * g.ny);
+    }
     s->nbodies = nbodies;
     s->moving = moving;
     s->device_mask = body_id == nullptr;
-    host_log("set_mask %p: %d bodies, moving %d, two steps per launch %d", (void *)s, nbodies,
-             moving ? 1 : 0, two_step_ok(s) ? 1 : 0);
     if (nbodies) HIP_TRY(hipMemcpyAsync(s->d_params, s->h_params, sizeof(BodyParams) * nbodies, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(launch_bodies(s->d_params, s->d_state, nbodies, s->t_dev, 0, s->stream));
     if (body_id) {
@@ -514,6 +540,13 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
     } else {
         HIP_TRY(launch_mask(s->mask, g, s->d_params, s->d_state, nbodies, 0, 0, g.nx, g.ny, s->stream));
     }
+    if (moving) {
+        // The other mask: the whole lattice now; each two-step launch then rebuilds its swept
+        // boxes at the first step's time, and those of the simulation's own at the second's.
+        HIP_TRY(launch_mask(s->mask_alt, g, s->d_params, s->d_state, nbodies, 0, 0, g.nx, g.ny, s->stream));
+    }
+    host_log("set_mask %p: %d bodies, moving %d, two steps per launch %d", (void *)s, nbodies,
+             moving ? 1 : 0, two_step_ok(s) ? 1 : 0);
     if (s->steps == 0) {
         HIP_TRY(launch_init(s->storage, step_args(s, s->cur ^ 1, 0), nullptr, nullptr, nullptr, s->cfg.rho0, s->cfg.ux0, s->cfg.uy0, s->stream));
         HIP_TRY(reset_outlet(s));

@@ -15,9 +15,9 @@ from tests.test_gpu_parity import CASES, build_case
 pytestmark = pytest.mark.gpu
 
 STORAGES = ["f64", "f32", "f32d", "f16s", "bf16s", "f16sr", "bf16sr"]
-# static masks without a convective outlet: the cases the two-step kernel takes
-STATIC = [c for c in CASES if not c[10] and c[7] != I.CHANNEL_CONVECTIVE]
-OTHER = [c for c in CASES if c[10] or c[7] == I.CHANNEL_CONVECTIVE]
+# every case without a convective outlet takes the two-step kernel (moving bodies included)
+TWO = [c for c in CASES if c[7] != I.CHANNEL_CONVECTIVE]
+OTHER = [c for c in CASES if c[7] == I.CHANNEL_CONVECTIVE]
 
 
 @contextlib.contextmanager
@@ -41,6 +41,7 @@ def make(case, ids, storage, fields, two_step, capfd=None):
             s.set_mask(ids, case.bodies)
     if capfd is not None:
         assert last_report(capfd) == int(two_step)
+    assert s.steps_per_launch == (2 if two_step else 1)
     s.init_fields(*fields)
     return s
 
@@ -65,7 +66,7 @@ def same_run(a, b, first, count, what):
 
 
 @pytest.mark.parametrize("storage", STORAGES)
-@pytest.mark.parametrize("spec", STATIC, ids=[c[0] for c in STATIC])
+@pytest.mark.parametrize("spec", TWO, ids=[c[0] for c in TWO])
 def test_two_step_bitwise_equals_one_step(gpu, capfd, spec, storage):
     """101 steps (three 32-step graph replays, two two-step launches and a one-step launch), then
     1 and 3 more: bitwise the same populations as one step per launch."""
@@ -84,14 +85,14 @@ def test_two_step_bitwise_equals_one_step(gpu, capfd, spec, storage):
 
 
 @pytest.mark.parametrize("spec", OTHER, ids=[c[0] for c in OTHER])
-def test_moving_bodies_and_convective_outlet_take_one_step_per_launch(gpu, capfd, spec):
-    """A mask rebuilt every step or a convective outlet keeps one step per launch."""
+def test_convective_outlet_takes_one_step_per_launch(gpu, capfd, spec):
+    """A convective outlet keeps one step per launch (its intermediate state is not kept)."""
     case, ids = build_case(*spec, seed=3)
     with env(VPLBM_LOG=1):
         s = gpu_sim(case, storage="f32", device_mask=ids is None)
         if ids is not None:
             s.set_mask(ids, case.bodies)
-    assert last_report(capfd) == 0
+    assert last_report(capfd) == 0 and s.steps_per_launch == 1
     s.close()
 
 
@@ -139,5 +140,21 @@ def test_two_step_full_size(gpu, nx, ny, storage, steps):
     a.step(steps)
     b.step(steps)
     same_run(a, b, 0, steps, f"{case.name}/{storage}")
+    a.close()
+    b.close()
+
+
+def test_two_step_oscillating_cylinder_full_size(gpu):
+    """The 8192 x 2048 oscillating cylinder (mask rebuilt on the device every step, swept box
+    only): two steps per launch with the second step's own mask, bitwise the one-step run."""
+    case = I.oscillating_cylinder_8192x2048()
+    fields = I.random_fields(case.nx, case.ny, 6, u_mean=case.u_in)
+    a = make(case, None, "f32", fields, True)
+    b = make(case, None, "f32", fields, False)
+    for n in (2, 37, 64):
+        a.step(n)
+        b.step(n)
+    same_run(a, b, 0, 103, "oscillating_cylinder_8192x2048")
+    assert np.array_equal(a.mask(), b.mask())
     a.close()
     b.close()
