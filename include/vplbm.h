@@ -185,10 +185,10 @@ int vplbm_steps_done(vplbm_sim s, int64_t *steps);
 int vplbm_stream(vplbm_sim s, void **stream);
 
 /* Lattice updates per kernel launch for this simulation: 2 when pairs of steps run in one launch
-   with the intermediate step kept on chip (any outlet but the convective one; moving bodies get
-   a second mask for the second step), else 1.  Either way the results are bitwise the same (the
-   update of Section 2 per node and step); the environment variable VPLBM_TWO_STEP=0 at create
-   forces 1.  EINVAL: bad handle or NULL out. */
+   with the intermediate step kept on chip (moving bodies get a second mask for the first step of
+   each pair), 1 when the environment variable VPLBM_TWO_STEP=0 was set at create.  An odd last
+   step of a call always takes a launch of its own.  Either way the results are bitwise the same
+   (the update of Section 2 per node and step).  EINVAL: bad handle or NULL out. */
 int vplbm_steps_per_launch(vplbm_sim s, int32_t *steps);
 
 /* Algorithmic HBM bytes of one lattice update for a storage format: 9 population loads,

@@ -346,7 +346,7 @@ class Simulation:
 
     @property
     def steps_per_launch(self):
-        """2 when pairs of steps share a launch (any outlet but the convective one), else 1."""
+        """2 when pairs of steps share a launch (the default), 1 with VPLBM_TWO_STEP=0."""
         return vplbm_steps_per_launch(self.h)
 
     @property

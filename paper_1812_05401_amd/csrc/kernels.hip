@@ -144,8 +144,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 // populations are bitwise those of two one-step launches, with one read and one write of the
 // planes instead of two of each.  The halo is computed twice (by this tile and its neighbour):
 // (TW + 2)(TH + 2) / (TW TH) of the nodes in phase 1.  Phase 1 takes the mask and body states of
-// step t, phase 2 those of step t + 1 (where bodies move, the host rebuilds two masks).  No
-// convective outlet: the host falls back to one step per launch.
+// step t, phase 2 those of step t + 1 (where bodies move, the host rebuilds two masks).  The
+// convective outlet's step-t values stay in LDS: phase 1 reads the previous ones from global
+// memory and keeps what it records for its own rows, phase 2 applies the outlet rule with them and
+// records step t + 1 for the next launch.
 // Tiles (measured): 128 x 8 for 4-byte storage (47 KB of LDS, three workgroups per CU), 64 x 8
 // for 8-byte storage (48 KB); for 2-byte storage 128 x 16 on large lattices (42 KB: less halo,
 // 10-13% faster at 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill
@@ -161,6 +163,8 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     static_assert((TW * TH) % kBlock2 == 0, "phase 2 gives every thread the same number of nodes");
     __shared__ E mid[9 * EN];                      // step t on the tile and its halo
     __shared__ double wave_acc[2][NW][kRingWidth]; // per-wave partials of steps t and t + 1
+    __shared__ T outl[3][TH];                      // convective outlet: step t's recorded values
+    constexpr int odirs[3] = {3, 6, 7};            // the directions entering from x = nx
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long t = *a.t_base + a.t_off;
     const Geom &g = a.g;
@@ -176,6 +180,7 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     const int x0 = (tile % ntx) * TW, y0 = (tile / ntx) * TH;
     const E *__restrict__ src = static_cast<const E *>(a.src);
     E *__restrict__ dst = static_cast<E *>(a.dst);
+    const Outlet out1{a.outlet.prev, nullptr, a.outlet.u};   // read the outlet, record nothing
     bool bad = false;
     double mass = 0.0;
 
@@ -200,7 +205,9 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         int id = 0;
         if (live) {
             T f[9];
-            pull<S>(src, x, y, g, a.outlet, f);
+            pull<S>(src, x, y, g, out1, f);
+            if (a.outlet.prev && x == g.nx - 1 && own)
+                for (int k = 0; k < 3; k++) outl[k][ly] = f[odirs[k]];
             const Macro<T> m = relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
             store_node<S>(mid, EN, unsigned(e), f, unsigned(y * g.pitch + x), (unsigned)t);
             if (own) {
@@ -232,6 +239,18 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         if ((x < g.nx) & (y < g.ny)) {
             T f[9];
             pull_tile<S>(mid, EN, EW, x, y, x0, y0, g, f);
+            if (a.outlet.prev && x == g.nx - 1) {
+                // the outlet rule of pull, with step t's values from LDS
+                const T u = T(a.outlet.u);
+                T *next = static_cast<T *>(a.outlet.next);
+                for (int k = 0; k < 3; k++) {
+                    int pa;
+                    const unsigned jn = tile_source(odirs[k], g.nx - 2, y, x0, y0, EW, g, pa);
+                    const T nb = C::load(mid + pa * EN, jn, weight<T>(odirs[k]));
+                    f[odirs[k]] = (outl[k][y - y0] + u * nb) / (T(1) + u);
+                }
+                for (int k = 0; k < 3; k++) next[k * g.ny + y] = f[odirs[k]];
+            }
             const Macro<T> m = relax_node(f, a.mask2, a.bodies2, g, a.p, x, y, id);
             const unsigned i = y * g.pitch + x;
             store_node<S, NT>(dst, g.plane, i, f, i, (unsigned)(t + 1));

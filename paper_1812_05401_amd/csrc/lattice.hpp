@@ -277,6 +277,21 @@ __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__
     }
 }
 
+// Element of a workgroup's LDS tile (see pull_tile) that direction a of node (x, y) pulls from,
+// and its plane in pa: edge_source without the periodic wrap, which the tile's halo holds.
+__device__ __forceinline__ unsigned tile_source(int a, int x, int y, int x0, int y0, int ew,
+                                                const Geom &g, int &pa)
+{
+    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr int mirror_y[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+    int sx = x - cx[a], sy = y - cy[a];
+    pa = a;
+    if ((sy < 0 || sy >= g.ny) && !g.yper) { sy = y; pa = mirror_y[a]; }
+    if ((sx < 0 || sx >= g.nx) && !g.xper) sx = sx < 0 ? 0 : g.nx - 1;
+    return unsigned((sy - y0 + 1) * ew + (sx - x0 + 1));
+}
+
 // Pull the nine shifted populations h of node (x, y) from a workgroup's tile in LDS instead of the
 // planes in global memory.  The tile holds the post-collision populations of the nodes
 // [x0 - 1, x0 + ew - 2] x [y0 - 1, ...] in unwrapped coordinates, ew per row, `plane` elements
@@ -304,15 +319,11 @@ __device__ __forceinline__ void pull_tile(const typename Codec<S>::elem *tile, u
         f[7] = C::load(tile + 7 * plane, e + E + 1, W<T>::diag);
         f[8] = C::load(tile + 8 * plane, e + E - 1, W<T>::diag);
     } else {
-        constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-        constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-        constexpr int mirror_y[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
 #pragma unroll
         for (int a = 0; a < 9; a++) {
-            int sx = x - cx[a], sy = y - cy[a], pa = a;
-            if ((sy < 0 || sy >= g.ny) && !g.yper) { sy = y; pa = mirror_y[a]; }
-            if ((sx < 0 || sx >= g.nx) && !g.xper) sx = sx < 0 ? 0 : g.nx - 1;
-            f[a] = C::load(tile + pa * plane, unsigned((sy - y0 + 1) * ew + (sx - x0 + 1)), weight<T>(a));
+            int pa;
+            const unsigned j = tile_source(a, x, y, x0, y0, ew, g, pa);
+            f[a] = C::load(tile + pa * plane, j, weight<T>(a));
         }
     }
 }

@@ -204,11 +204,10 @@ hipError_t reset_outlet(vplbm_sim s)
     return launch_outlet_init(s->storage, step_args(s, s->cur, 0), s->outlet[s->cur], s->stream);
 }
 
-// Two steps per launch need an outlet whose state the intermediate step need not record; moving
-// bodies take a second mask for the first step.
+// Two steps per launch: moving bodies take a second mask for the first step.
 bool two_step_ok(vplbm_sim s)
 {
-    return s->two_step && !s->outlet[0] && (!s->moving || s->mask_alt);
+    return s->two_step && (!s->moving || s->mask_alt);
 }
 
 // Enqueue n steps starting from the state in buf[first_src]: pairs of steps in two-step launches

@@ -15,9 +15,9 @@ from tests.test_gpu_parity import CASES, build_case
 pytestmark = pytest.mark.gpu
 
 STORAGES = ["f64", "f32", "f32d", "f16s", "bf16s", "f16sr", "bf16sr"]
-# every case without a convective outlet takes the two-step kernel (moving bodies included)
-TWO = [c for c in CASES if c[7] != I.CHANNEL_CONVECTIVE]
-OTHER = [c for c in CASES if c[7] == I.CHANNEL_CONVECTIVE]
+# every parity case takes the two-step kernel: static, spinning and moving bodies, host masks,
+# every edge combination and the convective outlet
+TWO = CASES
 
 
 @contextlib.contextmanager
@@ -84,18 +84,6 @@ def test_two_step_bitwise_equals_one_step(gpu, capfd, spec, storage):
     b.close()
 
 
-@pytest.mark.parametrize("spec", OTHER, ids=[c[0] for c in OTHER])
-def test_convective_outlet_takes_one_step_per_launch(gpu, capfd, spec):
-    """A convective outlet keeps one step per launch (its intermediate state is not kept)."""
-    case, ids = build_case(*spec, seed=3)
-    with env(VPLBM_LOG=1):
-        s = gpu_sim(case, storage="f32", device_mask=ids is None)
-        if ids is not None:
-            s.set_mask(ids, case.bodies)
-    assert last_report(capfd) == 0 and s.steps_per_launch == 1
-    s.close()
-
-
 def test_two_step_ring_and_restart(gpu):
     """Mixed call sizes with observations in between (each observation folds the last two steps),
     then a restart from populations at an odd step: ring entries and populations match the
@@ -128,12 +116,18 @@ def test_two_step_ring_and_restart(gpu):
     (8192, 2048, "f16s", 64),
     (8192, 2048, "f32", 64),
     (2100, 2001, "bf16sr", 21),
-], ids=["wake_2048x512_f32", "wake_8192x2048_f16s", "wake_8192x2048_f32", "ragged_tall_tiles_bf16sr"])
+    (6048, 2016, "f32", 65),
+], ids=["wake_2048x512_f32", "wake_8192x2048_f16s", "wake_8192x2048_f32", "ragged_tall_tiles_bf16sr",
+        "paper_re500_convective_f32"])
 def test_two_step_full_size(gpu, nx, ny, storage, steps):
     """The benchmark lattices in the launch configuration the benchmark times (graph replays of
-    two-step launches, non-temporal stores on the large lattice), and a ragged lattice large
-    enough for the tall 2-byte tiles."""
-    case = I.cylinder_wake(nx, ny, storage=storage)
+    two-step launches, non-temporal stores on the large lattice), a ragged lattice large enough
+    for the tall 2-byte tiles, and the paper's Re = 500 cylinder with its convective outlet."""
+    if (nx, ny) == (6048, 2016):
+        case = I.paper_cylinder_re500(storage=storage)
+    else:
+        case = I.cylinder_wake(nx, ny, storage=storage)
+    assert (case.nx, case.ny) == (nx, ny)
     fields = I.random_fields(case.nx, case.ny, 4, u_mean=case.u_in)
     a = make(case, None, storage, fields, True)
     b = make(case, None, storage, fields, False)
