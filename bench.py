@@ -9,8 +9,9 @@ walls, disk D = 64, Re = 200).  Its mask is static, so the library runs two step
 (the intermediate step kept in LDS); `one_step_per_launch` times the same workload with one step
 per launch, the memory-bound kernel.  The two population buffers (75 MB) fit in the 256 MB
 Infinity Cache, so the line also carries `hbm_resident`: the 8192 x 2048 oscillating-cylinder
-workload (FP32, mask rebuilt every step, so one step per launch), whose buffers (1.2 GB) do not,
-and `reduced_precision`: the 8192 x 2048 cylinder in every storage format.
+workload (FP32, mask rebuilt on the device every step), whose buffers (1.2 GB) do not, with and
+without two steps per launch, and `reduced_precision`: the 8192 x 2048 cylinder in every storage
+format.
 
 Prints one JSON line.  Inputs are synthetic (seeded geometry, uniform start) and resident on the
 GPU before timing starts.  `--copy-probe BYTES` instead times a plain device copy (the measured
@@ -107,14 +108,16 @@ def time_workload(case, steps, warmup, storage=None, two_step=True):
     # is noise).  Its algorithmic bytes are one read and one write of the planes plus the mask
     # whatever spl is: the two-step kernel keeps the intermediate step on chip.
     launch_s = gpu_ms / 1e3 / steps * spl
-    bytes_launch = bpu * case.nodes
+    # moving bodies: a two-step launch reads the masks of both of its steps (1 B per node more)
+    moving = any(b["freq"] != 0 and (b["ax"] != 0 or b["ay"] != 0) for b in case.bodies)
+    bytes_launch = (bpu + (1 if spl == 2 and moving else 0)) * case.nodes
     hbm = bytes_launch / launch_s / 1e9
     kernel = "vplbm::step2_kernel" if spl == 2 else "vplbm::step_kernel"
     roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(hbm / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(case.name, case.storage, spl),
             "kernel": kernel, "lattice_updates_per_launch": spl, "launch_us": round(launch_s * 1e6, 3),
-            "bytes_per_launch": bytes_launch, "bytes_per_node_per_launch": bpu}
+            "bytes_per_launch": bytes_launch, "bytes_per_node_per_launch": bytes_launch // case.nodes}
     valu = profile_entry("valu", case.name, case.storage, spl)
     if valu:
         # The kernel's VALU instructions (SQ_INSTS_VALU x 64 lanes per launch, from the committed
@@ -345,8 +348,12 @@ def main():
     if not args.no_extra:
         big = I.oscillating_cylinder_8192x2048()
         r = time_workload(big, 400, 40)
-        line["hbm_resident"] = {k: r[k] for k in ("workload", "storage", "mlups", "ms_per_step", "roofline")}
+        line["hbm_resident"] = {k: r[k] for k in ("workload", "storage", "mlups", "ms_per_step",
+                                                  "steps_per_launch", "roofline")}
         print(f"# {big.name}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        r1 = time_workload(I.oscillating_cylinder_8192x2048(), 400, 40, two_step=False)
+        line["hbm_resident"]["one_step_per_launch"] = {k: r1[k] for k in ("mlups", "ms_per_step", "roofline")}
+        print(f"# {big.name} one step per launch: {r1['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         red = {}
         for st in ("f64", "f32", "f32d", "f16s", "f16sr", "bf16s", "bf16sr"):
             c = I.cylinder_wake_8192x2048(st)
@@ -368,6 +375,7 @@ def main():
         cp = measure_copy(1 << 30, 20)
         line["copy_probe"] = cp
         for obj in [line["roofline"], line["hbm_resident"]["roofline"],
+                    line["hbm_resident"]["one_step_per_launch"]["roofline"],
                     line.get("one_step_per_launch", {}).get("roofline")]:
             if not obj:
                 continue

@@ -151,8 +151,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 // Tiles (measured): 128 x 8 for 4-byte storage (47 KB of LDS, three workgroups per CU), 64 x 8
 // for 8-byte storage (48 KB); for 2-byte storage 128 x 16 on large lattices (42 KB: less halo,
 // 10-13% faster at 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill
-// the chip.
-template <int S, int TW, int TH, bool NT>
+// the chip.  CONV: the lattice has a convective outlet (a separate instantiation: the outlet code
+// in the loops costs the 16-bit kernels about 20% even where it is skipped).
+template <int S, int TW, int TH, bool NT, bool CONV>
 __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
 {
     using C = Codec<S>;
@@ -180,7 +181,9 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     const int x0 = (tile % ntx) * TW, y0 = (tile / ntx) * TH;
     const E *__restrict__ src = static_cast<const E *>(a.src);
     E *__restrict__ dst = static_cast<E *>(a.dst);
-    const Outlet out1{a.outlet.prev, nullptr, a.outlet.u};   // read the outlet, record nothing
+    // Phase 1 reads the outlet and records nothing.  (Without a convective outlet prev is null at
+    // run time; making it null at compile time changes the schedule and costs 5-8%, measured.)
+    const Outlet out1{a.outlet.prev, nullptr, a.outlet.u};
     bool bad = false;
     double mass = 0.0;
 
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         if (live) {
             T f[9];
             pull<S>(src, x, y, g, out1, f);
-            if (a.outlet.prev && x == g.nx - 1 && own)
+            if (CONV && x == g.nx - 1 && own)
                 for (int k = 0; k < 3; k++) outl[k][ly] = f[odirs[k]];
             const Macro<T> m = relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
             store_node<S>(mid, EN, unsigned(e), f, unsigned(y * g.pitch + x), (unsigned)t);
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         if ((x < g.nx) & (y < g.ny)) {
             T f[9];
             pull_tile<S>(mid, EN, EW, x, y, x0, y0, g, f);
-            if (a.outlet.prev && x == g.nx - 1) {
+            if (CONV && x == g.nx - 1) {
                 // the outlet rule of pull, with step t's values from LDS
                 const T u = T(a.outlet.u);
                 T *next = static_cast<T *>(a.outlet.next);
@@ -334,8 +337,13 @@ template <int S, int TW, int TH>
 static void launch2(const StepArgs &a, hipStream_t st)
 {
     const dim3 grid(((a.g.nx + TW - 1) / TW) * ((a.g.ny + TH - 1) / TH)), block(kBlock2);
-    if (a.nt_store) step2_kernel<S, TW, TH, true><<<grid, block, 0, st>>>(a);
-    else step2_kernel<S, TW, TH, false><<<grid, block, 0, st>>>(a);
+    if (a.outlet.prev) {
+        if (a.nt_store) step2_kernel<S, TW, TH, true, true><<<grid, block, 0, st>>>(a);
+        else step2_kernel<S, TW, TH, false, true><<<grid, block, 0, st>>>(a);
+    } else {
+        if (a.nt_store) step2_kernel<S, TW, TH, true, false><<<grid, block, 0, st>>>(a);
+        else step2_kernel<S, TW, TH, false, false><<<grid, block, 0, st>>>(a);
+    }
 }
 
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st)
