@@ -2,9 +2,10 @@
 // replayed from a captured HIP graph (see the pool section of include/vplbm.h).
 //
 // Device side.  A descriptor per slot (buffers, geometry, parameters, admission step, target) and
-// a table of 64 x 4 tiles covering every resident simulation.  One workgroup per tile; each tile
+// a table of 64 x 8 tiles covering every resident simulation.  One workgroup per tile and two
+// steps per launch, the first kept in LDS as in the single-simulation two-step kernel; each tile
 // runs the same per-node update as the single-simulation step, so a simulation's fields do not
-// depend on its co-residents.  All resident simulations advance together, so a simulation's
+// depend on its co-residents or on the launch shape.  All resident simulations advance together, so a simulation's
 // steps done are the pool's step counter (on the device) minus its admission step: no per-step
 // bookkeeping launch is needed.  On a simulation's final step each tile writes its FP64 partial
 // sums (mass, body forces) to its own slot, summed in a fixed order inside the tile; at
@@ -37,8 +38,10 @@ using namespace vplbm;
 
 namespace vplbm {
 
-constexpr int kPoolTileW = 64, kPoolTileH = 4;   // one node per thread, 256 threads
+constexpr int kPoolTileW = 64, kPoolTileH = 8;   // 512 nodes: one per thread of kBlock2
+constexpr int kPoolEW = kPoolTileW + 2, kPoolEN = kPoolEW * (kPoolTileH + 2);
 constexpr int kPoolMaxSlots = 1024;
+static_assert(kPoolTileW * kPoolTileH == kBlock2, "one node per thread in the second step");
 
 struct PoolSim {
     void *buf[2];
@@ -50,6 +53,7 @@ struct PoolSim {
     int storage;
     int ntx, ntiles;
     int active;
+    int spl;                 // steps per graph replay (the pool's steps_per_launch)
     long long t0, target;    // pool step at admission; steps to run
     unsigned status;
     double obs[kRingWidth];  // folded final observables
@@ -65,76 +69,157 @@ struct TileRef {
     int slot, tile;
 };
 
-template <int S>
-__device__ __forceinline__ double pool_node(const PoolSim &d, long long done, int x, int y, double &fx,
-                                            double &fy, int &id)
+// Buffer holding a simulation's state after `done` steps.  Each graph replay of spl steps runs
+// ceil(spl / 2) launches from the replay's start, pairs of steps and an odd one last; a simulation
+// is admitted at a replay boundary, and a launch moves its state to the other buffer whether it
+// takes one step or two (one when the simulation has a single step left).
+__host__ __device__ inline int pool_buf(long long done, int spl)
 {
-    using C = Codec<S>;
-    using E = typename C::elem;
-    const int parity = (int)(done & 1);
-    const E *src = static_cast<const E *>(d.buf[parity]);
-    E *dst = static_cast<E *>(d.buf[parity ^ 1]);
-    const Outlet none{nullptr, nullptr, 0.0};
-    const auto m = update_node<S>(src, dst, d.mask, d.bodies, d.g, none, d.p, x, y, id, (unsigned)done);
-    fx = double(m.fx);
-    fy = double(m.fy);
-    return 1.0 + double(m.drho);
+    const long long launches = (done / spl) * ((spl + 1) / 2) + ((done % spl) + 1) / 2;
+    return (int)(launches & 1);
 }
 
-// One lattice step of every resident simulation: workgroup w (< *ntiles) updates one tile.
-__global__ __launch_bounds__(kBlock) void pool_step_kernel(PoolSim *sims, const TileRef *tiles,
-                                                           const int *ntiles,
-                                                           const long long *t_base, int t_off)
+// The final step's per-tile sums (mass, body forces): wave shuffles, then the waves in order,
+// into the tile's slot of the simulation's partials.  Called by every thread of the workgroup.
+__device__ __forceinline__ void pool_tile_partials(const PoolSim &d, int tile, double rho, double fx,
+                                                   double fy, int id, double (*part)[kRingWidth])
 {
-    __shared__ double part[kBlock / 64][kRingWidth];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < kRingWidth) part[wave][lane] = 0.0;
+    const double mw = wave_sum(rho);
+    if (lane == 0) part[wave][0] = mw;
+    unsigned long long solid = __ballot(id != 0);
+    while (solid) {
+        const int lead = __ffsll((unsigned long long)solid) - 1;
+        const int b = __shfl(id, lead, 64);
+        const bool mine = id == b;
+        const double sx = wave_sum(mine ? -fx : 0.0);
+        const double sy = wave_sum(mine ? -fy : 0.0);
+        if (lane == 0) {
+            part[wave][1 + 2 * (b - 1)] = sx;
+            part[wave][2 + 2 * (b - 1)] = sy;
+        }
+        solid &= ~__ballot(mine);
+    }
+    __syncthreads();
+    if (threadIdx.x < kRingWidth) {
+        double v = 0.0;
+        for (int w = 0; w < kBlock2 / 64; w++) v += part[w][threadIdx.x];
+        d.partials[(size_t)tile * kRingWidth + threadIdx.x] = v;
+    }
+}
+
+// One tile of one simulation for `nsteps` (1 or 2) steps from `done`: the node arithmetic of the
+// single-simulation kernels (update_node, or the two-step form with the first step kept in LDS),
+// so a simulation's fields do not depend on the launch shape or its co-residents.
+template <int S>
+__device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long done, int nsteps,
+                                          unsigned char *lds, double (*part)[kRingWidth])
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    using E = typename C::elem;
+    const Geom &g = d.g;
+    const int b = pool_buf(done, d.spl);
+    const E *__restrict__ src = static_cast<const E *>(d.buf[b]);
+    E *__restrict__ dst = static_cast<E *>(d.buf[b ^ 1]);
+    const Outlet none{nullptr, nullptr, 0.0};
+    const int x0 = (tile % d.ntx) * kPoolTileW, y0 = (tile / d.ntx) * kPoolTileH;
+    const int x = x0 + (threadIdx.x % kPoolTileW), y = y0 + (threadIdx.x / kPoolTileW);
+    const bool active = (x < g.nx) & (y < g.ny);
+    double rho = 0.0, fx = 0.0, fy = 0.0;
+    int id = 0;
+    bool bad = false;
+    if (nsteps == 1) {
+        if (active) {
+            const auto m = update_node<S>(src, dst, d.mask, d.bodies, g, none, d.p, x, y, id, (unsigned)done);
+            rho = 1.0 + double(m.drho);
+            fx = double(m.fx);
+            fy = double(m.fy);
+            bad = !(rho > 0.0 && rho < 1e30);
+        }
+    } else {
+        E *mid = reinterpret_cast<E *>(lds);
+        for (int it = 0; it < (kPoolEN + kBlock2 - 1) / kBlock2; it++) {
+            const int e = threadIdx.x + it * kBlock2;
+            const int lx = e % kPoolEW - 1, ly = e / kPoolEW - 1;
+            int hx = x0 + lx, hy = y0 + ly;
+            bool live = e < kPoolEN;
+            if (hx < 0 || hx >= g.nx) {
+                if (g.xper && hx >= -1 && hx <= g.nx) hx += hx < 0 ? g.nx : -g.nx;
+                else live = false;
+            }
+            if (hy < 0 || hy >= g.ny) {
+                if (g.yper && hy >= -1 && hy <= g.ny) hy += hy < 0 ? g.ny : -g.ny;
+                else live = false;
+            }
+            if (live) {
+                T f[9];
+                int hid;
+                pull<S>(src, hx, hy, g, none, f);
+                const auto m = relax_node(f, d.mask, d.bodies, g, d.p, hx, hy, hid);
+                store_node<S>(mid, kPoolEN, unsigned(e), f, unsigned(hy * g.pitch + hx), (unsigned)done);
+                const bool own = (lx >= 0) & (lx < kPoolTileW) & (ly >= 0) & (ly < kPoolTileH) &
+                                 (x0 + lx < g.nx) & (y0 + ly < g.ny);
+                const double r1 = 1.0 + double(m.drho);
+                bad |= own && !(r1 > 0.0 && r1 < 1e30);
+            }
+        }
+        __syncthreads();
+        if (active) {
+            T f[9];
+            pull_tile<S>(mid, kPoolEN, kPoolEW, x, y, x0, y0, g, f);
+            const auto m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
+            const unsigned i = y * g.pitch + x;
+            store_node<S>(dst, g.plane, i, f, i, (unsigned)(done + 1));
+            rho = 1.0 + double(m.drho);
+            fx = double(m.fx);
+            fy = double(m.fy);
+            bad |= !(rho > 0.0 && rho < 1e30);
+        }
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(const_cast<unsigned *>(&d.status), 1u);
+    if (done + nsteps == d.target) pool_tile_partials(d, tile, rho, fx, fy, id, part);
+}
+
+// Storage formats by arithmetic: class 1 computes in FP64 (F64, F32D), class 0 in FP32 with at
+// most 4-byte storage.  Each class has a kernel of its own, so the FP32 formats are not held to
+// the FP64 path's registers and LDS: measured 4 waves per SIMD with one kernel for all.
+__host__ __device__ inline int pool_class(int storage)
+{
+    return storage == kF64 || storage == kF32D ? 1 : 0;
+}
+
+// Steps t_off and t_off + 1 (nsteps = 2) or step t_off alone (nsteps = 1) of the graph replay, for
+// every resident simulation of class CLASS: workgroup w (< *ntiles) updates one tile (tiles of
+// the other class return at once); a simulation with a single step left takes it alone.
+template <int CLASS>
+__global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const TileRef *tiles,
+                                                            const int *ntiles,
+                                                            const long long *t_base, int t_off,
+                                                            int nsteps)
+{
+    // the first step's tile in the class's widest storage format
+    __shared__ __align__(16) unsigned char lds[9 * kPoolEN * (CLASS ? 8 : 4)];
+    __shared__ double part[kBlock2 / 64][kRingWidth];
     const int n = *ntiles;
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const TileRef tr = tiles[xcd_tile(blockIdx.x, n)];
     const PoolSim &d = sims[tr.slot];
     const long long done = *t_base + t_off - d.t0;
     if (!d.active || done < 0 || done >= d.target) return;    // uniform over the workgroup
-    const int x = (tr.tile % d.ntx) * kPoolTileW + lane;
-    const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
-    const bool active = (x < d.g.nx) & (y < d.g.ny);
-    double rho = 0.0, fx = 0.0, fy = 0.0;
-    int id = 0;
-    if (active) {
+    if (pool_class(d.storage) != CLASS) return;
+    const int k = d.target - done < nsteps ? 1 : nsteps;
+    if constexpr (CLASS == 1) {
+        if (d.storage == kF64) pool_tile<kF64>(d, tr.tile, done, k, lds, part);
+        else pool_tile<kF32D>(d, tr.tile, done, k, lds, part);
+    } else {
         switch (d.storage) {
-        case kF64: rho = pool_node<kF64>(d, done, x, y, fx, fy, id); break;
-        case kF32: rho = pool_node<kF32>(d, done, x, y, fx, fy, id); break;
-        case kF16S: rho = pool_node<kF16S>(d, done, x, y, fx, fy, id); break;
-        case kF32D: rho = pool_node<kF32D>(d, done, x, y, fx, fy, id); break;
-        case kF16SR: rho = pool_node<kF16SR>(d, done, x, y, fx, fy, id); break;
-        case kBF16SR: rho = pool_node<kBF16SR>(d, done, x, y, fx, fy, id); break;
-        default: rho = pool_node<kBF16S>(d, done, x, y, fx, fy, id); break;
-        }
-    }
-    const bool bad = active && !(rho > 0.0 && rho < 1e30);
-    if (__ballot(bad) && lane == 0) atomicOr(&sims[tr.slot].status, 1u);
-    if (done + 1 == d.target) {
-        // Final step: deterministic per-tile sums (wave shuffles, then the four waves in order).
-        if (lane < kRingWidth) part[wave][lane] = 0.0;
-        const double mw = wave_sum(rho);
-        if (lane == 0) part[wave][0] = mw;
-        unsigned long long solid = __ballot(id != 0);
-        while (solid) {
-            const int lead = __ffsll((unsigned long long)solid) - 1;
-            const int b = __shfl(id, lead, 64);
-            const bool mine = id == b;
-            const double sx = wave_sum(mine ? -fx : 0.0);
-            const double sy = wave_sum(mine ? -fy : 0.0);
-            if (lane == 0) {
-                part[wave][1 + 2 * (b - 1)] = sx;
-                part[wave][2 + 2 * (b - 1)] = sy;
-            }
-            solid &= ~__ballot(mine);
-        }
-        __syncthreads();
-        if (threadIdx.x < kRingWidth) {
-            double v = 0.0;
-            for (int w = 0; w < kBlock / 64; w++) v += part[w][threadIdx.x];
-            d.partials[(size_t)tr.tile * kRingWidth + threadIdx.x] = v;
+        case kF32: pool_tile<kF32>(d, tr.tile, done, k, lds, part); break;
+        case kF16S: pool_tile<kF16S>(d, tr.tile, done, k, lds, part); break;
+        case kF16SR: pool_tile<kF16SR>(d, tr.tile, done, k, lds, part); break;
+        case kBF16SR: pool_tile<kBF16SR>(d, tr.tile, done, k, lds, part); break;
+        default: pool_tile<kBF16S>(d, tr.tile, done, k, lds, part); break;
         }
     }
 }
@@ -178,11 +263,11 @@ __device__ __forceinline__ void pool_residual_node(const PoolSim &d, int parity,
 }
 
 // One workgroup per tile, as the step kernel; per-tile sums (waves in a fixed order).
-__global__ __launch_bounds__(kBlock) void pool_residual_kernel(PoolSim *sims, const TileRef *tiles,
-                                                               const int *ntiles,
-                                                               const long long *t_base, int t_off)
+__global__ __launch_bounds__(kBlock2) void pool_residual_kernel(PoolSim *sims, const TileRef *tiles,
+                                                                const int *ntiles,
+                                                                const long long *t_base, int t_off)
 {
-    __shared__ double part[kBlock / 64][2];
+    __shared__ double part[kBlock2 / 64][2];
     const int n = *ntiles;
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -194,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void pool_residual_kernel(PoolSim *sims, co
     const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
     double d2 = 0.0, u2 = 0.0;
     if (x < d.g.nx && y < d.g.ny) {
-        const int parity = (int)(done & 1);
+        const int parity = pool_buf(done, d.spl);
         switch (d.storage) {
         case kF64: pool_residual_node<kF64>(d, parity, x, y, d2, u2); break;
         case kF32: pool_residual_node<kF32>(d, parity, x, y, d2, u2); break;
@@ -214,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void pool_residual_kernel(PoolSim *sims, co
     __syncthreads();
     if (threadIdx.x < 2) {
         double v = 0.0;
-        for (int w = 0; w < kBlock / 64; w++) v += part[w][threadIdx.x];
+        for (int w = 0; w < kBlock2 / 64; w++) v += part[w][threadIdx.x];
         d.rpart[2 * tr.tile + threadIdx.x] = v;
     }
 }
@@ -314,6 +399,7 @@ struct vplbm_pool_s {
     hipGraphExec_t graph = nullptr;
     int grid_cap = 0;                     // workgroups per step launch in the captured graph
     bool graph_checks = false;            // the graph ends with the residual-check kernels
+    int graph_classes = 0;                // storage classes the graph has step kernels for
     PoolSim *d_sims = nullptr;
     TileRef *d_tiles = nullptr;
     int *d_ntiles = nullptr;
@@ -407,7 +493,7 @@ int retire(vplbm_pool p, int slot)
         r.ux.resize(n);
         r.uy.resize(n);
         StepArgs a{};
-        a.src = d.buf[done & 1];   // the state after `done` steps
+        a.src = d.buf[pool_buf(done, d.spl)];   // the state after `done` steps
         a.mask = d.mask;
         a.bodies = d.bodies;
         a.t_base = p->d_zero;
@@ -484,6 +570,7 @@ int admit(vplbm_pool p, Request &r, int slot)
     d.p = node_params(r.cfg);
     d.storage = r.cfg.storage;
     d.active = 1;
+    d.spl = p->cfg.steps_per_launch;
     d.t0 = p->t_host;
     d.target = r.nsteps;
     d.tol = r.tol;
@@ -515,9 +602,14 @@ int admit(vplbm_pool p, Request &r, int slot)
 int ensure_pool_graph(vplbm_pool p)
 {
     bool checks = false;
-    for (const PoolSim &d : p->h_sims) checks |= d.active && d.tol > 0.0;
+    int classes = 0;                      // bit c: a simulation of class c is resident
+    for (const PoolSim &d : p->h_sims) {
+        checks |= d.active && d.tol > 0.0;
+        if (d.active) classes |= 1 << pool_class(d.storage);
+    }
+    if (!classes) classes = 1;
     if (p->graph && p->grid_cap >= p->ntiles && p->grid_cap <= 8 * (p->ntiles > 4096 ? p->ntiles : 4096) &&
-        p->graph_checks == checks)
+        p->graph_checks == checks && p->graph_classes == classes)
         return VPLBM_OK;
     if (p->graph) {
         HIP_TRY(hipGraphExecDestroy(p->graph));
@@ -532,13 +624,21 @@ int ensure_pool_graph(vplbm_pool p)
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int j = 0; j < p->cfg.steps_per_launch && e == hipSuccess; j++) {
-        pool_step_kernel<<<dim3(cap), dim3(kBlock), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j);
-        e = hipGetLastError();
+    // pairs of steps from the replay's start, an odd one last (pool_buf counts launches this way)
+    for (int j = 0; j < p->cfg.steps_per_launch && e == hipSuccess; j += 2) {
+        const int nsteps = p->cfg.steps_per_launch - j >= 2 ? 2 : 1;
+        if (classes & 1) {
+            pool_step_kernel<0><<<dim3(cap), dim3(kBlock2), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j, nsteps);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess && (classes & 2)) {
+            pool_step_kernel<1><<<dim3(cap), dim3(kBlock2), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j, nsteps);
+            e = hipGetLastError();
+        }
     }
     if (e == hipSuccess && checks) {
         const int n = p->cfg.steps_per_launch;
-        pool_residual_kernel<<<dim3(cap), dim3(kBlock), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, n);
+        pool_residual_kernel<<<dim3(cap), dim3(kBlock2), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, n);
         e = hipGetLastError();
         if (e == hipSuccess) {
             pool_residual_fold_kernel<<<dim3(p->cfg.max_slots), dim3(64), 0, p->cap_stream>>>(p->d_sims, p->d_t, n);
@@ -550,6 +650,7 @@ int ensure_pool_graph(vplbm_pool p)
         e = hipGetLastError();
     }
     p->graph_checks = checks;
+    p->graph_classes = classes;
     hipError_t e2 = hipStreamEndCapture(p->cap_stream, &graph);
     if (e != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);

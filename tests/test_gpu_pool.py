@@ -246,3 +246,26 @@ def test_stochastic_rounding_is_the_same_in_the_pool(gpu, storage):
     _, srho, sux, suy = s.observables(fields=True)
     s.close()
     assert np.array_equal(rho, srho) and np.array_equal(ux, sux) and np.array_equal(uy, suy)
+
+
+@pytest.mark.parametrize("spl", [1, 7, 64])
+def test_launch_shapes_match_the_single_simulation_bitwise(gpu, spl):
+    """The pool takes pairs of steps per launch, an odd one last when steps_per_launch is odd, and
+    a single step for a request with one step left.  Over odd and even step counts and mixed
+    storage formats, the fields are bitwise those of the single-simulation path."""
+    B = gpu
+    cases = small_requests(seed=13, n=5)
+    for c, st, n in zip(cases, ("f32", "f16s", "f64", "f32d", "bf16sr"), (151, 200, 97, 64, 33)):
+        c.storage = st
+        c.steps = n
+    res, _ = run(B.Pool, cases, 1 << 30, spl=spl)
+    for k, c in enumerate(cases):
+        obs, fields = res[k]
+        assert obs["status"] == 0 and obs["step"] == c.steps - 1
+        s = B.Simulation(c, stream=None)
+        s.step(c.steps)
+        so, *sfields = s.observables(fields=True)
+        s.close()
+        for a, b in zip(fields, sfields):
+            assert np.array_equal(a, b), f"{c.name}/{c.storage}, {c.steps} steps, {spl} per launch"
+        assert abs(obs["mass"] - so["mass"]) <= 1e-13 * so["mass"]
