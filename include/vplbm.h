@@ -197,9 +197,10 @@ int vplbm_bytes_per_update(int32_t storage, int64_t *bytes);
 
 /* ---- serving pool -----------------------------------------------------------------------
  * Many independent simulations resident on one GPU at once, advanced together: every call to
- * vplbm_pool_advance replays one captured HIP graph of `steps_per_launch` launches of a
- * batched step kernel with one workgroup per tile of a device table spanning all resident
- * simulations (each simulation's per-node arithmetic is the single-simulation step's), then
+ * vplbm_pool_advance replays one captured HIP graph of `steps_per_launch` steps of a batched
+ * step kernel (two steps per launch with the first kept on chip, an odd one last) with one
+ * workgroup per tile of a device table spanning all resident simulations (each simulation's
+ * per-node arithmetic is the single-simulation step's), then
  * retires the finished ones and admits queued requests, first come first served, while the
  * memory budget and the slots allow.  A simulation's results do not depend on what else is
  * resident: fields are bitwise identical alone and in a mix, and the final mass and body forces
@@ -236,8 +237,8 @@ int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *b
 
 /* Admission cap on the lattice nodes of the resident simulations (0, the default: none).  A
    queued request is admitted only while the resident nodes plus its own stay within the cap, or
-   when nothing is resident.  Resident simulations advance in lock step, one step per launch each,
-   so every resident node slows every other simulation down: a cap near what fills the GPU keeps
+   when nothing is resident.  Resident simulations advance in lock step, every launch taking each
+   of them the same steps, so every resident node slows every other simulation down: a cap near what fills the GPU keeps
    small requests batched while long ones do not crowd each other, which shortens the tail of
    time-to-result at high load.  Takes effect at the next vplbm_pool_advance. */
 int vplbm_pool_set_admission(vplbm_pool p, uint64_t max_resident_nodes);
