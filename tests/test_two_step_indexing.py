@@ -1,0 +1,141 @@
+"""CPU models of the two-step kernels' index arithmetic, checked against the one-step edge rule
+and the launch sequence.  They restate, in Python, what step2_kernel / pool_tile compute for each
+thread (the halo mapping of the first step, the LDS offsets of the second, the outlet lookups)
+and what pool_buf counts, and check the invariants the kernels rely on: every LDS read is in
+bounds and falls on a node the first step wrote, that node is the one the global rule
+(edge_source) names, every lattice node is owned by exactly one tile, and the buffer pool_buf
+names is the one the launch sequence leaves the state in."""
+import itertools
+import random
+
+import pytest
+
+CX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+CY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+MIRROR_Y = [0, 1, 4, 3, 2, 8, 7, 6, 5]
+
+
+def edge_source(a, x, y, nx, ny, xper, yper):
+    """The one-step kernel's source of direction a at node (x, y) (global coordinates)."""
+    sx, sy, pa = x - CX[a], y - CY[a], a
+    if sy < 0 or sy >= ny:
+        if yper:
+            sy += ny if sy < 0 else -ny
+        else:
+            sy, pa = y, MIRROR_Y[a]
+    if sx < 0 or sx >= nx:
+        if xper:
+            sx += nx if sx < 0 else -nx
+        else:
+            sx = 0 if sx < 0 else nx - 1
+    return sx, sy, pa
+
+
+def tile_source(a, x, y, x0, y0, ew, nx, ny, xper, yper):
+    """The two-step kernel's LDS element and plane for direction a of node (x, y)."""
+    sx, sy, pa = x - CX[a], y - CY[a], a
+    if (sy < 0 or sy >= ny) and not yper:
+        sy, pa = y, MIRROR_Y[a]
+    if (sx < 0 or sx >= nx) and not xper:
+        sx = 0 if sx < 0 else nx - 1
+    return (sy - y0 + 1) * ew + (sx - x0 + 1), pa
+
+
+def first_step(nx, ny, xper, yper, x0, y0, tw, th, nthreads):
+    """Phase 1: LDS element -> the global node it holds, and the tile's own nodes."""
+    ew, en = tw + 2, (tw + 2) * (th + 2)
+    written, own = {}, set()
+    for it in range(-(-en // nthreads)):
+        for tid in range(nthreads):
+            e = tid + it * nthreads
+            lx, ly = e % ew - 1, e // ew - 1
+            ux, uy = x0 + lx, y0 + ly
+            x, y, live = ux, uy, e < en
+            if x < 0 or x >= nx:
+                if xper and -1 <= x <= nx:
+                    x += nx if x < 0 else -nx
+                else:
+                    live = False
+            if y < 0 or y >= ny:
+                if yper and -1 <= y <= ny:
+                    y += ny if y < 0 else -ny
+                else:
+                    live = False
+            if live:
+                assert 0 <= x < nx and 0 <= y < ny
+                written[e] = (x, y)
+                if 0 <= lx < tw and 0 <= ly < th and ux < nx and uy < ny:
+                    own.add((x, y))
+    return written, own
+
+
+def check_lattice(nx, ny, xper, yper, tw, th, nthreads=512, outlet=False):
+    ew, en = tw + 2, (tw + 2) * (th + 2)
+    ntx, nty = -(-nx // tw), -(-ny // th)
+    owned = []
+    for tile in range(ntx * nty):
+        x0, y0 = (tile % ntx) * tw, (tile // ntx) * th
+        written, own = first_step(nx, ny, xper, yper, x0, y0, tw, th, nthreads)
+        owned += own
+        for j in range(tw * th):
+            x, y = x0 + j % tw, y0 + j // tw
+            if not (x < nx and y < ny):
+                continue
+            for a in range(9):
+                idx, pa = tile_source(a, x, y, x0, y0, ew, nx, ny, xper, yper)
+                assert 0 <= idx < en and idx in written, (nx, ny, x, y, a)
+                assert (written[idx], pa) == (edge_source(a, x, y, nx, ny, xper, yper)[:2],
+                                              edge_source(a, x, y, nx, ny, xper, yper)[2])
+            if outlet and x == nx - 1:
+                # the convective rule's neighbour: direction a of node (nx - 2, y)
+                assert (x, y) in own
+                for a in (3, 6, 7):
+                    idx, pa = tile_source(a, nx - 2, y, x0, y0, ew, nx, ny, xper, yper)
+                    sx, sy, spa = edge_source(a, nx - 2, y, nx, ny, xper, yper)
+                    assert idx in written and written[idx] == (sx, sy) and pa == spa
+    assert sorted(owned) == sorted((x, y) for x in range(nx) for y in range(ny))
+
+
+SIZES = [(1, 1), (2, 3), (5, 7), (64, 8), (128, 8), (130, 9), (200, 17), (257, 31), (129, 1),
+         (1, 20), (90, 60)]
+
+
+@pytest.mark.parametrize("tw,th", [(128, 8), (64, 8), (128, 16)])
+def test_second_step_reads_what_the_first_wrote(tw, th):
+    for (nx, ny), xper, yper in itertools.product(SIZES, (0, 1), (0, 1)):
+        check_lattice(nx, ny, xper, yper, tw, th)
+
+
+@pytest.mark.parametrize("tw,th", [(128, 8), (64, 8), (128, 16)])
+def test_convective_outlet_lookups(tw, th):
+    for (nx, ny), yper in itertools.product([(2, 3), (5, 7), (129, 9), (150, 40), (257, 31)], (0, 1)):
+        check_lattice(nx, ny, 0, yper, tw, th, outlet=True)
+
+
+def pool_buf(done, spl):
+    """The pool's buffer after `done` steps (pool.hip): launches counted per graph replay."""
+    launches = (done // spl) * ((spl + 1) // 2) + ((done % spl) + 1) // 2
+    return launches & 1
+
+
+def test_pool_buffer_follows_the_launch_sequence():
+    """Replays of spl steps in pairs from the replay's start (an odd one last), a request with one
+    step left taking it alone, and early stops that lower the target to a replay boundary + 1."""
+    rng = random.Random(1)
+    for spl in list(range(1, 12)) + [63, 64]:
+        for _ in range(100):
+            target = rng.randint(1, 5 * spl + 7)
+            stop_at = rng.randint(1, max(1, target // spl)) * spl if rng.random() < 0.5 else None
+            buf, done, tgt = 0, 0, target
+            while done < tgt:
+                for j in range(0, spl, 2):
+                    if done >= tgt:
+                        break
+                    n = 2 if spl - j >= 2 else 1
+                    k = 1 if tgt - done < n else n
+                    assert pool_buf(done, spl) == buf
+                    buf ^= 1
+                    done += k
+                    assert pool_buf(done, spl) == buf
+                if stop_at is not None and done == stop_at and tgt > done + 1:
+                    tgt = done + 1
