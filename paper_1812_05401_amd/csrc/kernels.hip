@@ -1,10 +1,11 @@
 // HIP kernels of the VP-LBM library for gfx950 (MI355X).
 //
-// The step is one fused, memory-bound pass: per node 9 pulled population loads, a 1-byte mask
-// load, the moments / penalization / collision in registers, 9 coalesced stores, and the FP64
-// per-step reductions (wave64 shuffles, one LDS hop, FP64 atomics into sub-slots that the next
-// step folds into a device ring).  Nothing here is a dense contraction, so there is no MFMA; the
-// roofline is HBM bandwidth.
+// The step is one fused pass: per node 9 pulled population loads, a 1-byte mask load, the
+// moments / penalization / collision in registers, 9 coalesced stores, and the FP64 per-step
+// reductions (wave64 shuffles, one LDS hop, FP64 atomics into sub-slots that a later launch folds
+// into a device ring).  One step per launch it is bound by HBM bandwidth; the two-step kernel
+// keeps the first of two steps in LDS and moves the planes once per two steps.  Nothing here is a
+// dense contraction, so there is no MFMA.
 #include <stdlib.h>
 
 #include "kernels.hpp"

@@ -211,8 +211,8 @@ bool two_step_ok(vplbm_sim s)
 }
 
 // Enqueue n steps starting from the state in buf[first_src]: pairs of steps in two-step launches
-// where allowed, else (and for an odd last step) one step per launch.  Every launch moves the state
-// to the other buffer; *flip is the parity of the number of launches.
+// (unless VPLBM_TWO_STEP=0 turned them off), one step per launch for an odd last step.  Every
+// launch moves the state to the other buffer; *flip is the parity of the number of launches.
 hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st, int *flip)
 {
     const bool two = two_step_ok(s);
