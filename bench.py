@@ -10,8 +10,8 @@ walls, disk D = 64, Re = 200).  Its mask is static, so the library runs two step
 per launch, the memory-bound kernel.  The two population buffers (75 MB) fit in the 256 MB
 Infinity Cache, so the line also carries `hbm_resident`: the 8192 x 2048 oscillating-cylinder
 workload (FP32, mask rebuilt on the device every step), whose buffers (1.2 GB) do not, with and
-without two steps per launch, and `reduced_precision`: the 8192 x 2048 cylinder in every storage
-format.
+without two steps per launch, `reduced_precision`: the 8192 x 2048 cylinder in every storage
+format, and `paper_cylinder_re500`: the paper's 6048 x 2016 Re = 500 case (convective outlet).
 
 Prints one JSON line.  Inputs are synthetic (seeded geometry, uniform start) and resident on the
 GPU before timing starts.  `--copy-probe BYTES` instead times a plain device copy (the measured
@@ -361,6 +361,15 @@ def main():
             red[st] = {k: r[k] for k in ("mlups", "ms_per_step", "steps_per_launch", "roofline")}
             print(f"# {c.name}/{st}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         line["reduced_precision"] = {"workload": "cylinder_wake_8192x2048", **red}
+        # the paper's own Re = 500 cylinder (6048 x 2016, SRT, convective outlet), FP32
+        pc = {}
+        for two in (True, False):
+            r = time_workload(I.paper_cylinder_re500("f32"), 400, 40, two_step=two)
+            pc["two_steps_per_launch" if two else "one_step_per_launch"] = {
+                k: r[k] for k in ("mlups", "ms_per_step", "steps_per_launch", "roofline")}
+            print(f"# paper_cylinder_re500 ({'two' if two else 'one'} per launch): {r['mlups']:.0f} MLUPS",
+                  file=sys.stderr, flush=True)
+        line["paper_cylinder_re500"] = {"workload": "paper_cylinder_re500", "storage": "f32", **pc}
         # FP32 square channels from cache-resident to far beyond the 256 MB Infinity Cache
         sweep = []
         for n, steps in ((2048, 400), (4096, 200), (8192, 60)):
