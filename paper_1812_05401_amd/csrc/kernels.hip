@@ -149,10 +149,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 // convective outlet's step-t values stay in LDS: phase 1 reads the previous ones from global
 // memory and keeps what it records for its own rows, phase 2 applies the outlet rule with them and
 // records step t + 1 for the next launch.
-// Tiles (measured): 128 x 8 for 4-byte storage (47 KB of LDS, three workgroups per CU), 64 x 8
-// for 8-byte storage (48 KB); for 2-byte storage 128 x 16 on large lattices (42 KB: less halo,
-// 10-13% faster at 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill
-// the chip.  CONV: the lattice has a convective outlet (a separate instantiation: the outlet code
+// Tiles (measured): 128 x 8 for FP32 (47 KB of LDS, three workgroups per CU); 64 x 8 for the
+// FP64-arithmetic formats (F64: 48 KB; F32D: 24 KB, 25-36% faster than 128 x 8 under its 94
+// VGPRs); for 2-byte storage 128 x 16 on large lattices (42 KB: less halo, 10-13% faster at
+// 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill the chip.  CONV: the lattice has a convective outlet (a separate instantiation: the outlet code
 // in the loops costs the 16-bit kernels about 20% even where it is skipped).
 template <int S, int TW, int TH, bool NT, bool CONV>
 __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
@@ -355,7 +355,7 @@ hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st)
     switch (storage) {
     case kF64: launch2<kF64, 64, 8>(a, st); break;
     case kF32: launch2<kF32, 128, 8>(a, st); break;
-    case kF32D: launch2<kF32D, 128, 8>(a, st); break;
+    case kF32D: launch2<kF32D, 64, 8>(a, st); break;
     case kF16S: VPLBM_STEP2(kF16S); break;
     case kBF16S: VPLBM_STEP2(kBF16S); break;
     case kF16SR: VPLBM_STEP2(kF16SR); break;
