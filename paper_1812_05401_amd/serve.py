@@ -11,9 +11,10 @@ import numpy as np
 from . import binding as B
 
 # Admission cap for serving: resident lattice nodes enough to fill the GPU four times over
-# (256 CUs x 8 resident workgroups x 256 nodes per workgroup x 4).  Measured on the 256-request
-# stream at 1.2x capacity: p50 0.20 s / p99 1.07 s with the cap, 0.29 s / 2.50 s without.
-DEFAULT_RESIDENT_NODES = 256 * 8 * 256 * 4
+# (256 CUs x 4 resident workgroups x 512 nodes per workgroup x 4).  Measured on the 256-request
+# stream at 1.2x capacity: p50 0.21 s / p99 1.00 s with the cap, 0.26 s / 2.04 s without
+# (python -m paper_1812_05401_amd.serve --cap-sweep).
+DEFAULT_RESIDENT_NODES = 256 * 4 * 512 * 4
 
 
 def _percentiles(ttr):
@@ -94,3 +95,45 @@ def _summary(order, done_at, wall, **extra):
     out.update(_percentiles(ttr))
     out.update(extra)
     return out
+
+
+def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4_000_000),
+              n_requests=256, budget_bytes=2 << 30):
+    """The serving stream at each offered load (relative to `capacity_glups`) through the pool at
+    each admission cap; one line per run."""
+    import dataclasses
+    from . import inputs as I
+    base = I.serving_requests(n=n_requests, rate_per_s=1.0)
+    mean_lups = sum(r.case.nodes * r.case.steps for r in base) / len(base)
+    cap_rps = capacity_glups * 1e9 / mean_lups
+    for load in loads:
+        reqs = [dataclasses.replace(r, arrival=r.arrival / (load * cap_rps)) for r in base]
+        for cap in caps:
+            st, _ = run_pool(reqs, budget_bytes, max_slots=128, steps_per_launch=64,
+                             max_resident_nodes=cap)
+            print(f"load {load} cap {cap:>8d}: p50 {st['p50_s']:.3f} p99 {st['p99_s']:.3f} "
+                  f"mean {st['mean_s']:.3f} max {st['max_s']:.3f} GLUPS {st['aggregate_mlups'] / 1e3:.1f} "
+                  f"running<= {st['max_running']}", flush=True)
+
+
+def main():
+    import argparse
+    ap = argparse.ArgumentParser(description="serving measurements on one GPU")
+    ap.add_argument("--cap-sweep", action="store_true",
+                    help="time-to-result of the request stream at each admission cap and load")
+    ap.add_argument("--capacity-glups", type=float, default=63.5,
+                    help="capacity the offered loads are relative to (the plain FP32 step)")
+    ap.add_argument("--loads", default="1.2,0.7")
+    ap.add_argument("--caps", default="0,1000000,2000000,4000000")
+    args = ap.parse_args()
+    if not args.cap_sweep:
+        ap.error("nothing to do (try --cap-sweep)")
+    import torch
+    torch.cuda.set_device(0)
+    B.load()
+    cap_sweep(args.capacity_glups, tuple(float(x) for x in args.loads.split(",")),
+              tuple(int(x) for x in args.caps.split(",")))
+
+
+if __name__ == "__main__":
+    main()
