@@ -188,6 +188,11 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     bool bad = false;
     double mass = 0.0;
 
+    // A tile two or more nodes from every edge: every node of phase 1 (the halo included) pulls
+    // by plain shifts and needs no wrap, and so does every node of phase 2 (same loads, same
+    // values, fewer instructions).
+    const bool inner = (x0 >= 2) & (x0 + TW + 2 <= g.nx) & (y0 >= 2) & (y0 + TH + 2 <= g.ny);
+
     // Phase 1.  Halo nodes across a periodic edge are the wrapped nodes; halo positions outside
     // a non-periodic edge (and beyond a ragged tile) are skipped: no phase-2 pull reads them.
     for (int it = 0; it < (EN + kBlock2 - 1) / kBlock2; it++) {
@@ -195,21 +200,26 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         const int lx = e % EW - 1, ly = e / EW - 1;
         const int ux = x0 + lx, uy = y0 + ly;     // unwrapped
         int x = ux, y = uy;
-        bool live = e < EN;
-        if (x < 0 || x >= g.nx) {
-            if (g.xper && x >= -1 && x <= g.nx) x += x < 0 ? g.nx : -g.nx;
-            else live = false;
+        bool live = e < EN, own;
+        if (inner) {
+            own = live & (lx >= 0) & (lx < TW) & (ly >= 0) & (ly < TH);
+        } else {
+            if (x < 0 || x >= g.nx) {
+                if (g.xper && x >= -1 && x <= g.nx) x += x < 0 ? g.nx : -g.nx;
+                else live = false;
+            }
+            if (y < 0 || y >= g.ny) {
+                if (g.yper && y >= -1 && y <= g.ny) y += y < 0 ? g.ny : -g.ny;
+                else live = false;
+            }
+            own = live & (lx >= 0) & (lx < TW) & (ly >= 0) & (ly < TH) & (ux < g.nx) & (uy < g.ny);
         }
-        if (y < 0 || y >= g.ny) {
-            if (g.yper && y >= -1 && y <= g.ny) y += y < 0 ? g.ny : -g.ny;
-            else live = false;
-        }
-        const bool own = live & (lx >= 0) & (lx < TW) & (ly >= 0) & (ly < TH) & (ux < g.nx) & (uy < g.ny);
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if (live) {
             T f[9];
-            pull<S>(src, x, y, g, out1, f);
+            if (inner) pull_interior<S>(src, x, y, g, f);
+            else pull<S>(src, x, y, g, out1, f);
             if (CONV && x == g.nx - 1 && own)
                 for (int k = 0; k < 3; k++) outl[k][ly] = f[odirs[k]];
             const Macro<T> m = relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
@@ -242,7 +252,8 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         int id = 0;
         if ((x < g.nx) & (y < g.ny)) {
             T f[9];
-            pull_tile<S>(mid, EN, EW, x, y, x0, y0, g, f);
+            if (inner) pull_tile_shifts<S>(mid, EN, EW, x, y, x0, y0, f);
+            else pull_tile<S>(mid, EN, EW, x, y, x0, y0, g, f);
             if (CONV && x == g.nx - 1) {
                 // the outlet rule of pull, with step t's values from LDS
                 const T u = T(a.outlet.u);

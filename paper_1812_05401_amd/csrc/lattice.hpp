@@ -229,6 +229,27 @@ __device__ __forceinline__ int edge_source(int a, int x, int y, const Geom &g, i
     return sy * g.pitch + sx;
 }
 
+// Pull of a node with all eight neighbours inside the lattice (0 < x < nx-1, 0 < y < ny-1): nine
+// plain shifts.  Every index below is >= pitch - 1 >= 0 there.
+template <int S>
+__device__ __forceinline__ void pull_interior(const typename Codec<S>::elem *__restrict__ src, int x,
+                                              int y, const Geom &g, typename Codec<S>::real f[9])
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    const unsigned P = g.pitch;
+    const unsigned i = y * P + x;
+    f[0] = C::load(src, i, W<T>::rest);
+    f[1] = C::load(src + 1 * g.plane, i - 1, W<T>::axis);
+    f[2] = C::load(src + 2 * g.plane, i - P, W<T>::axis);
+    f[3] = C::load(src + 3 * g.plane, i + 1, W<T>::axis);
+    f[4] = C::load(src + 4 * g.plane, i + P, W<T>::axis);
+    f[5] = C::load(src + 5 * g.plane, i - P - 1, W<T>::diag);
+    f[6] = C::load(src + 6 * g.plane, i - P + 1, W<T>::diag);
+    f[7] = C::load(src + 7 * g.plane, i + P + 1, W<T>::diag);
+    f[8] = C::load(src + 8 * g.plane, i + P - 1, W<T>::diag);
+}
+
 // Pull the nine shifted populations h of node (x, y) from the post-collision planes `src`.
 template <int S>
 __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__ src, int x, int y,
@@ -236,19 +257,9 @@ __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__
 {
     using C = Codec<S>;
     using T = typename C::real;
-    const unsigned P = g.pitch;
-    const unsigned i = y * P + x;
     const bool interior = (x > 0) & (x < g.nx - 1) & (y > 0) & (y < g.ny - 1);
-    if (interior) {                        // every index below is >= P - 1 >= 0 here
-        f[0] = C::load(src, i, W<T>::rest);
-        f[1] = C::load(src + 1 * g.plane, i - 1, W<T>::axis);
-        f[2] = C::load(src + 2 * g.plane, i - P, W<T>::axis);
-        f[3] = C::load(src + 3 * g.plane, i + 1, W<T>::axis);
-        f[4] = C::load(src + 4 * g.plane, i + P, W<T>::axis);
-        f[5] = C::load(src + 5 * g.plane, i - P - 1, W<T>::diag);
-        f[6] = C::load(src + 6 * g.plane, i - P + 1, W<T>::diag);
-        f[7] = C::load(src + 7 * g.plane, i + P + 1, W<T>::diag);
-        f[8] = C::load(src + 8 * g.plane, i + P - 1, W<T>::diag);
+    if (interior) {
+        pull_interior<S>(src, x, y, g, f);
     } else {
 #pragma unroll
         for (int a = 0; a < 9; a++) {
@@ -298,6 +309,28 @@ __device__ __forceinline__ unsigned tile_source(int a, int x, int y, int x0, int
 // per population: a periodic neighbour across an edge sits in the tile's halo, so for the tile
 // only the free-slip and clamped edges of edge_source remain.  Every node the pull reads lies
 // within one node of (x, y), inside the tile.
+// The tile pull of a node whose nine sources are plain shifts (no free-slip or clamped edge next to
+// it): every index below is >= 0, the tile having a halo.
+template <int S>
+__device__ __forceinline__ void pull_tile_shifts(const typename Codec<S>::elem *tile, unsigned plane,
+                                                 int ew, int x, int y, int x0, int y0,
+                                                 typename Codec<S>::real f[9])
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    const unsigned e = unsigned((y - y0 + 1) * ew + (x - x0 + 1));
+    const unsigned E = unsigned(ew);
+    f[0] = C::load(tile, e, W<T>::rest);
+    f[1] = C::load(tile + 1 * plane, e - 1, W<T>::axis);
+    f[2] = C::load(tile + 2 * plane, e - E, W<T>::axis);
+    f[3] = C::load(tile + 3 * plane, e + 1, W<T>::axis);
+    f[4] = C::load(tile + 4 * plane, e + E, W<T>::axis);
+    f[5] = C::load(tile + 5 * plane, e - E - 1, W<T>::diag);
+    f[6] = C::load(tile + 6 * plane, e - E + 1, W<T>::diag);
+    f[7] = C::load(tile + 7 * plane, e + E + 1, W<T>::diag);
+    f[8] = C::load(tile + 8 * plane, e + E - 1, W<T>::diag);
+}
+
 template <int S>
 __device__ __forceinline__ void pull_tile(const typename Codec<S>::elem *tile, unsigned plane, int ew,
                                           int x, int y, int x0, int y0, const Geom &g,
@@ -305,19 +338,9 @@ __device__ __forceinline__ void pull_tile(const typename Codec<S>::elem *tile, u
 {
     using C = Codec<S>;
     using T = typename C::real;
-    const unsigned e = unsigned((y - y0 + 1) * ew + (x - x0 + 1));
-    const unsigned E = unsigned(ew);
     const bool shifts = (g.xper | ((x > 0) & (x < g.nx - 1))) & (g.yper | ((y > 0) & (y < g.ny - 1)));
-    if (shifts) {                          // every index below is >= 0 (the tile has a halo)
-        f[0] = C::load(tile, e, W<T>::rest);
-        f[1] = C::load(tile + 1 * plane, e - 1, W<T>::axis);
-        f[2] = C::load(tile + 2 * plane, e - E, W<T>::axis);
-        f[3] = C::load(tile + 3 * plane, e + 1, W<T>::axis);
-        f[4] = C::load(tile + 4 * plane, e + E, W<T>::axis);
-        f[5] = C::load(tile + 5 * plane, e - E - 1, W<T>::diag);
-        f[6] = C::load(tile + 6 * plane, e - E + 1, W<T>::diag);
-        f[7] = C::load(tile + 7 * plane, e + E + 1, W<T>::diag);
-        f[8] = C::load(tile + 8 * plane, e + E - 1, W<T>::diag);
+    if (shifts) {
+        pull_tile_shifts<S>(tile, plane, ew, x, y, x0, y0, f);
     } else {
 #pragma unroll
         for (int a = 0; a < 9; a++) {

@@ -77,6 +77,11 @@ def check_lattice(nx, ny, xper, yper, tw, th, nthreads=512, outlet=False):
         x0, y0 = (tile % ntx) * tw, (tile // ntx) * th
         written, own = first_step(nx, ny, xper, yper, x0, y0, tw, th, nthreads)
         owned += own
+        if x0 >= 2 and x0 + tw + 2 <= nx and y0 >= 2 and y0 + th + 2 <= ny:
+            # the kernels' interior fast path: no wrap, every first-step node pulls by plain
+            # shifts (pull_interior), every second-step node too (pull_tile_shifts)
+            assert len(written) == en
+            assert all(0 < x < nx - 1 and 0 < y < ny - 1 for x, y in written.values())
         for j in range(tw * th):
             x, y = x0 + j % tw, y0 + j // tw
             if not (x < nx and y < ny):
@@ -97,7 +102,7 @@ def check_lattice(nx, ny, xper, yper, tw, th, nthreads=512, outlet=False):
 
 
 SIZES = [(1, 1), (2, 3), (5, 7), (64, 8), (128, 8), (130, 9), (200, 17), (257, 31), (129, 1),
-         (1, 20), (90, 60)]
+         (1, 20), (90, 60), (400, 40)]
 
 
 @pytest.mark.parametrize("tw,th", [(128, 8), (64, 8), (128, 16)])
