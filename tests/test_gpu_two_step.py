@@ -152,3 +152,24 @@ def test_two_step_oscillating_cylinder_full_size(gpu):
     assert np.array_equal(a.mask(), b.mask())
     a.close()
     b.close()
+
+
+def test_two_step_without_reductions_and_with_a_short_ring(gpu):
+    """Reductions off: the populations are those of the reduced run, bitwise.  A ring of 16 steps
+    over 101 steps (the folds wrap around it): its last 16 entries match one step per launch."""
+    spec = CASES[2]
+    case, ids = build_case(*spec, seed=31)
+    fields = I.random_fields(case.nx, case.ny, 31, u_mean=case.u_in)
+    with env(VPLBM_TWO_STEP=1):
+        a = gpu_sim(case, storage="f32", reduce=False)
+        b = gpu_sim(case, storage="f32", ring=16)
+    with env(VPLBM_TWO_STEP=0):
+        c = gpu_sim(case, storage="f32", ring=16)
+    for s in (a, b, c):
+        s.init_fields(*fields)
+        s.step(101)
+    assert a.steps_per_launch == 2 and b.steps_per_launch == 2 and c.steps_per_launch == 1
+    assert np.array_equal(a.populations(), b.populations())
+    same_run(b, c, 85, 16, "ring of 16")
+    for s in (a, b, c):
+        s.close()
