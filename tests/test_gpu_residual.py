@@ -53,13 +53,15 @@ def _drain(pool, ids):
     return out
 
 
-def test_pool_early_stop(gpu):
+@pytest.mark.parametrize("spl,every", [(64, 256), (7, 280)])
+def test_pool_early_stop(gpu, spl, every):
     """A steady plane-shear run with an early stop retires at the first check whose residual is
     below the tolerance, one step after it; its result is the single-simulation run of as many
     steps.  A run whose tolerance is never met runs all its steps, and a run without a stop is
-    not affected."""
+    not affected.  With an odd steps_per_launch the final step after the stop is the single step
+    of a replay's first launch."""
     B = gpu
-    spl, every, tol = 64, 256, 1e-6
+    tol = 1e-6
     steady = S.shear_case("srt", 0.5 + math.sqrt(6) / 4).case
     never = S.shear_case("mrt", 1.5, 3 / 16, nx=32).case
     plain = I.Case("plain", 90, 60, collision="mrt", tau=0.7, bc=I.CHANNEL, u_in=(0.04, 0.0),

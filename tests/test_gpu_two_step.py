@@ -176,3 +176,23 @@ def test_two_step_without_reductions_and_with_a_short_ring(gpu):
     same_run(b, c, 85, 16, "ring of 16")
     for s in (a, b, c):
         s.close()
+
+
+def test_bodies_start_moving_mid_run(gpu):
+    """Static bodies for 33 steps, then the same bodies set oscillating (the second mask is
+    allocated then, after the graphs were captured), 65 more: bitwise the one-step path."""
+    import copy
+    case = I.cylinder_wake(300, 120, d=20.0, x0=80.0, re=100.0, storage="f32")
+    moving = [dict(b, ax=0.0, ay=4.0, freq=0.01) for b in case.bodies]
+    fields = I.random_fields(case.nx, case.ny, 8, u_mean=case.u_in)
+    a = make(case, None, "f32", fields, True)
+    b = make(case, None, "f32", fields, False)
+    for s in (a, b):
+        s.step(33)
+        s.set_mask(None, moving)
+        s.step(65)
+    assert a.steps_per_launch == 2 and b.steps_per_launch == 1
+    same_run(a, b, 0, 98, "bodies start moving")
+    assert np.array_equal(a.mask(), b.mask())
+    a.close()
+    b.close()
