@@ -152,8 +152,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 // Tiles (measured): 128 x 8 for FP32 (47 KB of LDS, three workgroups per CU); 64 x 8 for the
 // FP64-arithmetic formats (F64: 48 KB; F32D: 24 KB, 25-36% faster than 128 x 8 under its 94
 // VGPRs); for 2-byte storage 128 x 16 on large lattices (42 KB: less halo, 10-13% faster at
-// 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill the chip.  CONV: the lattice has a convective outlet (a separate instantiation: the outlet code
-// in the loops costs the 16-bit kernels about 20% even where it is skipped).
+// 8192 x 2048) and 128 x 8 on smaller ones, whose taller tiles would not fill the chip.
+// CONV: the lattice has a convective outlet (a separate instantiation: the outlet code in the
+// loops costs the 16-bit kernels about 20% even where it is skipped).
 template <int S, int TW, int TH, bool NT, bool CONV>
 __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
 {
@@ -485,7 +486,6 @@ template <int S>
 __global__ __launch_bounds__(kBlock) void encode_kernel(StepArgs a, const double *pop)
 {
     using C = Codec<S>;
-    using T = typename C::real;
     using E = typename C::elem;
     const int node = blockIdx.x * kBlock + threadIdx.x;
     const int n = a.g.nx * a.g.ny;
@@ -501,7 +501,6 @@ template <int S>
 __global__ __launch_bounds__(kBlock) void decode_kernel(StepArgs a, double *pop)
 {
     using C = Codec<S>;
-    using T = typename C::real;
     using E = typename C::elem;
     const int node = blockIdx.x * kBlock + threadIdx.x;
     const int n = a.g.nx * a.g.ny;
