@@ -98,9 +98,9 @@ def _summary(order, done_at, wall, **extra):
 
 
 def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4_000_000),
-              n_requests=256, budget_bytes=2 << 30):
+              n_requests=256, budget_bytes=2 << 30, fifo=False):
     """The serving stream at each offered load (relative to `capacity_glups`) through the pool at
-    each admission cap; one line per run."""
+    each admission cap (and, with fifo, one request at a time); one line per run."""
     import dataclasses
     from . import inputs as I
     base = I.serving_requests(n=n_requests, rate_per_s=1.0)
@@ -114,6 +114,11 @@ def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4
             print(f"load {load} cap {cap:>8d}: p50 {st['p50_s']:.3f} p99 {st['p99_s']:.3f} "
                   f"mean {st['mean_s']:.3f} max {st['max_s']:.3f} GLUPS {st['aggregate_mlups'] / 1e3:.1f} "
                   f"running<= {st['max_running']}", flush=True)
+        if fifo:
+            st = run_fifo(reqs)
+            print(f"load {load} fifo        : p50 {st['p50_s']:.3f} p99 {st['p99_s']:.3f} "
+                  f"mean {st['mean_s']:.3f} max {st['max_s']:.3f} GLUPS {st['aggregate_mlups'] / 1e3:.1f}",
+                  flush=True)
 
 
 def main():
@@ -125,6 +130,7 @@ def main():
                     help="capacity the offered loads are relative to (the plain FP32 step)")
     ap.add_argument("--loads", default="1.2,0.7")
     ap.add_argument("--caps", default="0,1000000,2000000,4000000")
+    ap.add_argument("--fifo", action="store_true", help="also run each load one request at a time")
     args = ap.parse_args()
     if not args.cap_sweep:
         ap.error("nothing to do (try --cap-sweep)")
@@ -132,7 +138,7 @@ def main():
     torch.cuda.set_device(0)
     B.load()
     cap_sweep(args.capacity_glups, tuple(float(x) for x in args.loads.split(",")),
-              tuple(int(x) for x in args.caps.split(",")))
+              tuple(int(x) for x in args.caps.split(",")), fifo=args.fifo)
 
 
 if __name__ == "__main__":
