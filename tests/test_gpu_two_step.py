@@ -196,3 +196,42 @@ def test_bodies_start_moving_mid_run(gpu):
     assert np.array_equal(a.mask(), b.mask())
     a.close()
     b.close()
+
+
+def test_two_step_random_configurations(gpu):
+    """24 seeded random configurations: lattice sizes from 2 x 1 to 300 x 200, every edge
+    combination (periodic, channel, periodic in x with free-slip walls, convective outlet),
+    0-3 bodies (static, spinning or oscillating), every storage format and 1-41 steps; the
+    populations and ring values of two steps per launch against one step per launch."""
+    from paper_1812_05401_amd import binding as B
+    rng = np.random.default_rng(2024)
+    pfs = (I.PERIODIC, I.PERIODIC, I.FREESLIP, I.FREESLIP)
+    bcs = [I.ALL_PERIODIC, I.CHANNEL, pfs, I.CHANNEL_CONVECTIVE]
+    done = 0
+    for k in range(24):
+        nx, ny = int(rng.integers(2, 301)), int(rng.integers(1, 201))
+        bc = bcs[int(rng.integers(len(bcs)))]
+        storage = STORAGES[int(rng.integers(len(STORAGES)))]
+        nb = int(rng.integers(0, 4)) if min(nx, ny) >= 12 else 0
+        moving = bool(rng.random() < 0.4)
+        bodies = I.random_bodies(nx, ny, 100 + k, nb, moving=moving, rmin=1.5,
+                                 rmax=max(2.0, min(nx, ny) / 5)) if nb else []
+        u_in = (0.04, 0.0) if bc[0] == I.VELOCITY else (0.0, 0.0)
+        case = I.Case(f"random{k}", nx, ny, collision="mrt" if k % 2 else "srt",
+                      tau=float(rng.uniform(0.55, 1.2)), lam=3 / 16, bc=bc, u_in=u_in, u0=u_in,
+                      bodies=bodies, storage=storage)
+        fields = I.random_fields(nx, ny, 200 + k, u_mean=u_in)
+        steps = int(rng.integers(1, 42))
+        try:
+            a = make(case, None, storage, fields, True)
+        except B.VplbmError as e:              # a lattice the edge rules do not admit
+            assert e.code == B.EINVAL, e
+            continue
+        b = make(case, None, storage, fields, False)
+        a.step(steps)
+        b.step(steps)
+        same_run(a, b, 0, steps, f"{case.name} {nx}x{ny} {bc} {storage} {len(bodies)} bodies, {steps} steps")
+        a.close()
+        b.close()
+        done += 1
+    assert done >= 20
