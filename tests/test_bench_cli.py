@@ -26,3 +26,21 @@ def test_entry_module_exposes_build_and_smoke():
     sys.path.insert(0, ROOT)
     import __graft_entry__ as g
     assert callable(g.build) and callable(g.smoke)
+
+
+def test_profile_entries_follow_the_kernel_source(tmp_path, monkeypatch):
+    """bench.py reads a counter summary only when it was taken on the current kernel source, and
+    looks entries up by workload, storage and updates per launch."""
+    sys.path.insert(0, ROOT)
+    import json
+    import bench
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps({
+        "w/f32/2": {"bytes_per_launch": 123, "source_digest": "a" * 16},
+        "w/f32/1": {"bytes_per_launch": 456, "source_digest": "b" * 16}}))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_digest", lambda: "a" * 16)
+    assert bench.measured_traffic("w", "f32", 2) == 123
+    assert bench.measured_traffic("w", "f32", 1) is None      # taken on other sources
+    assert bench.measured_traffic("w", "f16s", 2) is None     # not measured
+    assert bench.profile_entry("valu", "w", "f32", 2) is None  # no such summary
