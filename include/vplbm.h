@@ -246,7 +246,7 @@ int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *b
 int vplbm_pool_set_admission(vplbm_pool p, uint64_t max_resident_nodes);
 
 /* Early stop for a steady run (a QUEUED request): every `every` >= 1 steps (checked at the end of
-   each launch, so at multiples of steps_per_launch at the earliest) the pool computes the
+   each graph replay, so at multiples of steps_per_launch at the earliest) the pool computes the
    request's convergence residual on the device, as vplbm_residual defines it with u_prev the
    field of the previous check, and once it is below `tol` > 0 the request runs one more step
    (whose mass and forces are reduced) and finishes.  It costs 16 bytes per node more, charged
@@ -257,8 +257,9 @@ int vplbm_pool_set_stop(vplbm_pool p, int64_t id, double tol, int64_t every);
    check); valid until vplbm_pool_result releases the request. */
 int vplbm_pool_residual(vplbm_pool p, int64_t id, double *residual);
 
-/* Wait for the previous launch, retire finished simulations, admit queued ones, and launch the
-   next chunk of steps (asynchronous).  Any output pointer may be NULL. */
+/* Wait for the previous graph replay, retire finished simulations, admit queued ones, and replay
+   the graph for the next steps_per_launch steps (asynchronous).  Any output pointer may be
+   NULL. */
 int vplbm_pool_advance(vplbm_pool p, int32_t *running, int32_t *queued, int32_t *finished_total);
 
 /* Cancel a request.  A QUEUED one leaves the queue at once; a RUNNING one is retired at the next
