@@ -247,9 +247,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--precision-study", default="", metavar="WORKLOAD",
-                    help="instead of the benchmark: run WORKLOAD (cylinder_wake_2048x512 or "
-                         "cylinder_wake_8192x2048) in every storage format for --steps steps and "
-                         "print the comparison against FP64")
+                    help="instead of the benchmark: run WORKLOAD (cylinder_wake_2048x512, "
+                         "cylinder_wake_8192x2048, paper_cylinder_re500 or "
+                         "oscillating_cylinder_8192x2048) in the storage formats of --storages for "
+                         "--steps steps and print the comparison against FP64")
     ap.add_argument("--dump", default="", help="with --precision-study: .npz for the series")
     ap.add_argument("--sweep", default="", choices=["", "fig3", "fig12", "table1", "fig5", "fig14"],
                     help="instead of the benchmark: run one of the paper's parameter sweeps "
@@ -302,7 +303,8 @@ def main():
         from paper_1812_05401_amd import study
         mk = {"cylinder_wake_2048x512": I.cylinder_wake_2048x512,
               "cylinder_wake_8192x2048": lambda: I.cylinder_wake_8192x2048("f32"),
-              "paper_cylinder_re500": I.paper_cylinder_re500}[args.precision_study]
+              "paper_cylinder_re500": I.paper_cylinder_re500,
+              "oscillating_cylinder_8192x2048": I.oscillating_cylinder_8192x2048}[args.precision_study]
         res = study.compare_storages(mk(), args.steps, dump=args.dump or None,
                                      storages=tuple(args.storages.split(",")),
                                      me_every=args.me_every,
