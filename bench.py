@@ -394,7 +394,7 @@ def main():
     if not args.no_serving:
         line["serving"] = serving_leg(args.serving_requests, (0.7, 1.2), 2 << 30, (0.7, 1.2))
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(I.cylinder_wake_2048x512(), 40)
+        line["cpu_baseline"] = cpu_baseline(I.cylinder_wake_2048x512(), 100)
     print(json.dumps(line), flush=True)
 
 
