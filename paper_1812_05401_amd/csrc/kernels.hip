@@ -118,8 +118,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if (active) {
-            const Macro<T> m = update_node<S, NT>(src, dst, a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id,
-                                                  (unsigned)t);
+            const Macro<T> m = update_node<S, NT, mask_first_one_step<S, NT>()>(
+                src, dst, a.mask, a.bodies, a.g, a.outlet, a.p, x, y, id, (unsigned)t);
             const double rho_d = 1.0 + double(m.drho);
             mass += rho_d;
             fx_d = double(m.fx);
@@ -163,6 +163,7 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     using E = typename C::elem;
     constexpr int EW = TW + 2, EN = EW * (TH + 2);
     constexpr int NW = kBlock2 / 64;
+    constexpr bool MF = mask_first_two_step<S, NT>();   // mask byte loaded before the populations
     static_assert((TW * TH) % kBlock2 == 0, "phase 2 gives every thread the same number of nodes");
     __shared__ E mid[9 * EN];                      // step t on the tile and its halo
     __shared__ double wave_acc[2][NW][kRingWidth]; // per-wave partials of steps t and t + 1
@@ -218,12 +219,14 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if (live) {
+            if constexpr (MF) id = *at(a.mask, unsigned(y * g.pitch + x));
             T f[9];
             if (inner) pull_interior<S>(src, x, y, g, f);
             else pull<S>(src, x, y, g, out1, f);
             if (CONV && x == g.nx - 1 && own)
                 for (int k = 0; k < 3; k++) outl[k][ly] = f[odirs[k]];
-            const Macro<T> m = relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
+            const Macro<T> m = MF ? relax_node_id(f, id, a.bodies, g, a.p, x, y)
+                                  : relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
             store_node<S>(mid, EN, unsigned(e), f, unsigned(y * g.pitch + x), (unsigned)t);
             if (own) {
                 const double rho_d = 1.0 + double(m.drho);
@@ -252,6 +255,7 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
         double fx_d = 0.0, fy_d = 0.0;
         int id = 0;
         if ((x < g.nx) & (y < g.ny)) {
+            if constexpr (MF) id = *at(a.mask2, unsigned(y * g.pitch + x));
             T f[9];
             if (inner) pull_tile_shifts<S>(mid, EN, EW, x, y, x0, y0, f);
             else pull_tile<S>(mid, EN, EW, x, y, x0, y0, g, f);
@@ -267,7 +271,8 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
                 }
                 for (int k = 0; k < 3; k++) next[k * g.ny + y] = f[odirs[k]];
             }
-            const Macro<T> m = relax_node(f, a.mask2, a.bodies2, g, a.p, x, y, id);
+            const Macro<T> m = MF ? relax_node_id(f, id, a.bodies2, g, a.p, x, y)
+                                  : relax_node(f, a.mask2, a.bodies2, g, a.p, x, y, id);
             const unsigned i = y * g.pitch + x;
             store_node<S, NT>(dst, g.plane, i, f, i, (unsigned)(t + 1));
             const double rho_d = 1.0 + double(m.drho);
