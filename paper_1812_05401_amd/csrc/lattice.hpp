@@ -608,11 +608,37 @@ observe_node(const typename Codec<S>::elem *__restrict__ src, const uint8_t *__r
 
 // ---- wave reductions ------------------------------------------------------------------------------
 
+// v from another lane of the same row of 16, by a DPP lane pattern (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(int(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double lane_double(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(b), lane);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum of v over the 64 lanes of a wave (every lane active), the same value in every lane.  Within
+// each row of 16 lanes, four DPP exchanges add lane pairs, then quads, then half-rows: lane i
+// with i ^ 1, with i ^ 2, with the mirrored lane of the other quad, with the mirrored lane of the
+// other half-row (FP addition commutes, so both partners hold the same sum after each step).
+// The four row sums are read from lanes 0, 16, 32 and 48 and added in a fixed order.  No LDS
+// round trips, unlike a butterfly of lane shuffles.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_double<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_double<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_double<0x141>(v);   // row_half_mirror
+    v += dpp_double<0x140>(v);   // row_mirror
+    return (lane_double(v, 0) + lane_double(v, 16)) + (lane_double(v, 32) + lane_double(v, 48));
 }
 
 // Map a hardware workgroup id to a logical tile so that each XCD (workgroups are dealt to the 8
