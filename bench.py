@@ -104,7 +104,7 @@ def time_workload(case, steps, warmup, storage=None, two_step=True):
     if obs["status"] != 0:
         raise RuntimeError(f"{case.name}: unstable")
     bpu = B.vplbm_bytes_per_update(case.storage)
-    # One launch updates every node spl times (the graph's step-counter kernel, one per 32 steps,
+    # One launch updates every node spl times (the graph's step-counter kernel, one per 128 steps,
     # is noise).  Its algorithmic bytes are one read and one write of the planes plus the mask
     # whatever spl is: the two-step kernel keeps the intermediate step on chip.
     launch_s = gpu_ms / 1e3 / steps * spl
@@ -238,8 +238,8 @@ def copy_probe(nbytes, reps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6000)
-    ap.add_argument("--warmup", type=int, default=600)
+    ap.add_argument("--steps", type=int, default=6144)     # 48 graph replays of 128 steps
+    ap.add_argument("--warmup", type=int, default=768)
     ap.add_argument("--workload", default="cylinder_wake_2048x512")
     ap.add_argument("--storage", default="", help="storage format of the workload (default: its own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -25,6 +25,8 @@ __device__ __forceinline__ double *acc_set(const StepArgs &a, long long t)
 // adds the lanes, so a result does not depend on which workgroup folds or when.  One memory round
 // trip for both steps.  Nothing is cleared, so folding a step again gives the same value: a step
 // is folded by the next launch and, when that launch starts one step later, by the one after.
+// The fold always takes the shuffle form of the wave sum, so that every fold of a step (by either
+// kernel class, or by an observation) writes the same value.
 __device__ __forceinline__ void fold_recent(const StepArgs &a, long long t, int q)
 {
     const int lane = threadIdx.x & 63;
@@ -34,8 +36,8 @@ __device__ __forceinline__ void fold_recent(const StepArgs &a, long long t, int 
         v1 += s1[b * kRingWidth + q];
         v2 += s2[b * kRingWidth + q];
     }
-    v1 = wave_sum(v1);
-    v2 = wave_sum(v2);
+    v1 = wave_sum<false>(v1);
+    v2 = wave_sum<false>(v2);
     if (lane == 0) {
         if (t >= 1) a.ring[(size_t)((t - 1) % a.ring_len) * kRingWidth + q] = v1;
         if (t >= 2) a.ring[(size_t)((t - 2) % a.ring_len) * kRingWidth + q] = v2;
@@ -73,6 +75,7 @@ __device__ __forceinline__ void add_partials(const StepArgs &a, long long t, con
 
 // Body forces of one row of nodes: only waves holding solid nodes do any work, one pass per
 // body id present in the wave; lane 0 adds the wave's sums into the wave's own LDS partials.
+template <bool DPP>
 __device__ __forceinline__ void wave_forces(double *wave_acc, double fx, double fy, int id)
 {
     unsigned long long solid = __ballot(id != 0);
@@ -80,8 +83,8 @@ __device__ __forceinline__ void wave_forces(double *wave_acc, double fx, double 
         const int lead = __ffsll((unsigned long long)solid) - 1;
         const int k = __shfl(id, lead, 64);
         const bool mine = id == k;
-        const double sx = wave_sum(mine ? -fx : 0.0);
-        const double sy = wave_sum(mine ? -fy : 0.0);
+        const double sx = wave_sum<DPP>(mine ? -fx : 0.0);
+        const double sy = wave_sum<DPP>(mine ? -fy : 0.0);
         if ((threadIdx.x & 63) == 0) {
             wave_acc[1 + 2 * (k - 1)] += sx;
             wave_acc[2 + 2 * (k - 1)] += sy;
@@ -95,6 +98,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 {
     using C = Codec<S>;
     using T = typename C::real;
+    constexpr bool DPP = wave_sum_dpp<T>();
     using E = typename C::elem;
     // Per-wave partial sums: each wave writes only its own row (LDS accesses of one wave are in
     // order), so the workgroup needs a single barrier, before the rows are added.
@@ -126,10 +130,10 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
             fy_d = double(m.fy);
             bad |= !(rho_d > 0.0 && rho_d < 1e30);   // also catches NaN
         }
-        if (a.reduce) wave_forces(wave_acc[wave], fx_d, fy_d, id);
+        if (a.reduce) wave_forces<DPP>(wave_acc[wave], fx_d, fy_d, id);
     }
     if (a.reduce) {
-        const double mw = wave_sum(mass);
+        const double mw = wave_sum<DPP>(mass);
         if (lane == 0) wave_acc[wave][0] = mw;
         if (__ballot(bad) && lane == 0) atomicOr(a.status, 1u);
         __syncthreads();
@@ -164,6 +168,7 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     constexpr int EW = TW + 2, EN = EW * (TH + 2);
     constexpr int NW = kBlock2 / 64;
     constexpr bool MF = mask_first_two_step<S, NT>();   // mask byte loaded before the populations
+    constexpr bool DPP = wave_sum_dpp<T>();
     static_assert((TW * TH) % kBlock2 == 0, "phase 2 gives every thread the same number of nodes");
     __shared__ E mid[9 * EN];                      // step t on the tile and its halo
     __shared__ double wave_acc[2][NW][kRingWidth]; // per-wave partials of steps t and t + 1
@@ -238,10 +243,10 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
                 id = 0;                           // another tile's node: not in this tile's sums
             }
         }
-        if (a.reduce) wave_forces(wave_acc[0][wave], fx_d, fy_d, id);
+        if (a.reduce) wave_forces<DPP>(wave_acc[0][wave], fx_d, fy_d, id);
     }
     if (a.reduce) {
-        const double mw = wave_sum(mass);
+        const double mw = wave_sum<DPP>(mass);
         if (lane == 0) wave_acc[0][wave][0] = mw;
     }
     mass = 0.0;
@@ -281,10 +286,10 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
             fy_d = double(m.fy);
             bad |= !(rho_d > 0.0 && rho_d < 1e30);
         }
-        if (a.reduce) wave_forces(wave_acc[1][wave], fx_d, fy_d, id);
+        if (a.reduce) wave_forces<DPP>(wave_acc[1][wave], fx_d, fy_d, id);
     }
     if (a.reduce) {
-        const double mw = wave_sum(mass);
+        const double mw = wave_sum<DPP>(mass);
         if (lane == 0) wave_acc[1][wave][0] = mw;
         if (__ballot(bad) && lane == 0) atomicOr(a.status, 1u);
         __syncthreads();

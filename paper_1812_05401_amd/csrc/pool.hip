@@ -81,20 +81,21 @@ __host__ __device__ inline int pool_buf(long long done, int spl)
 
 // The final step's per-tile sums (mass, body forces): wave shuffles, then the waves in order,
 // into the tile's slot of the simulation's partials.  Called by every thread of the workgroup.
+template <bool DPP>
 __device__ __forceinline__ void pool_tile_partials(const PoolSim &d, int tile, double rho, double fx,
                                                    double fy, int id, double (*part)[kRingWidth])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane < kRingWidth) part[wave][lane] = 0.0;
-    const double mw = wave_sum(rho);
+    const double mw = wave_sum<DPP>(rho);
     if (lane == 0) part[wave][0] = mw;
     unsigned long long solid = __ballot(id != 0);
     while (solid) {
         const int lead = __ffsll((unsigned long long)solid) - 1;
         const int b = __shfl(id, lead, 64);
         const bool mine = id == b;
-        const double sx = wave_sum(mine ? -fx : 0.0);
-        const double sy = wave_sum(mine ? -fy : 0.0);
+        const double sx = wave_sum<DPP>(mine ? -fx : 0.0);
+        const double sy = wave_sum<DPP>(mine ? -fy : 0.0);
         if (lane == 0) {
             part[wave][1 + 2 * (b - 1)] = sx;
             part[wave][2 + 2 * (b - 1)] = sy;
@@ -179,7 +180,7 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
         }
     }
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(const_cast<unsigned *>(&d.status), 1u);
-    if (done + nsteps == d.target) pool_tile_partials(d, tile, rho, fx, fy, id, part);
+    if (done + nsteps == d.target) pool_tile_partials<wave_sum_dpp<T>()>(d, tile, rho, fx, fy, id, part);
 }
 
 // Storage formats by arithmetic: class 1 computes in FP64 (F64, F32D), class 0 in FP32 with at

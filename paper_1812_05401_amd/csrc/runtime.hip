@@ -76,9 +76,13 @@ int elem_bytes(int storage)
 
 namespace {
 
+// Steps per captured graph replay.  128 (measured): 1.2% faster than 32 on the cache-resident
+// 2048 x 512 lattice, where the step-counter node and the gap between replays are a visible share
+// of a 22 us launch pair; no change on large lattices.  Calls of fewer steps are launched
+// directly.
 int graph_chunk()
 {
-    int k = 32;
+    int k = 128;
     if (const char *e = getenv("VPLBM_GRAPH_STEPS")) k = atoi(e);
     if (k < 0) k = 0;
     return k & ~1;   // even: a replay is whole two-step launches where those apply

@@ -118,12 +118,12 @@ def test_graph_replay_equals_single_steps(gpu):
     b = gpu_sim(case)
     a.init_fields(*fields)
     b.init_fields(*fields)
-    a.step(96)
-    for _ in range(96):
+    a.step(300)                                   # two 128-step graph replays and 44 launches
+    for _ in range(300):
         b.step(1)
     assert np.array_equal(a.populations(), b.populations())
     oa, ob = a.observables(), b.observables()
-    assert oa["step"] == ob["step"] == 95
+    assert oa["step"] == ob["step"] == 299
     assert abs(oa["mass"] - ob["mass"]) <= 1e-13 * abs(ob["mass"])
 
 
@@ -185,18 +185,21 @@ def test_unstable_state_is_reported(gpu):
 
 def test_full_size_cylinder_2048x512(gpu):
     """The 2048 x 512 cylinder wake at its full size, in FP64 and in the FP32 the benchmark
-    times, 40 steps from the uniform start (one graph chunk plus single launches)."""
+    times, from the uniform start: FP32 after 40 steps (single launches), FP64 after 130 (one
+    128-step graph replay, then a two-step launch)."""
     case = I.cylinder_wake_2048x512()
     o = oracle_sim(case)
     o.step(40)
-    g64 = gpu_sim(case, storage="f64")
-    g64.step(40)
-    assert max(compare(o, g64, TOL64, "cylinder_2048x512_f64")) <= TOL64
     g32 = gpu_sim(case, storage="f32")
     g32.step(40)
     eg, er, eu, em, ef = compare(o, g32, 0, "cylinder_2048x512_f32")
     # FP32: a few roundings of ~6e-8 per step on populations of size <= 0.45
     assert eg < 1e-5 and er < 1e-5 and eu < 1e-4 and em < 1e-6 and ef < 1e-4
+    g32.close()
+    o.step(90)
+    g64 = gpu_sim(case, storage="f64")
+    g64.step(130)
+    assert max(compare(o, g64, TOL64, "cylinder_2048x512_f64")) <= TOL64
 
 
 def test_full_size_paper_cylinder_re500(gpu):

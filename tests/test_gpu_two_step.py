@@ -34,8 +34,9 @@ def env(**kw):
                 os.environ[k] = v
 
 
-def make(case, ids, storage, fields, two_step, capfd=None):
-    with env(VPLBM_TWO_STEP=int(two_step), VPLBM_LOG=1):
+def make(case, ids, storage, fields, two_step, capfd=None, graph_steps=None):
+    extra = {} if graph_steps is None else {"VPLBM_GRAPH_STEPS": graph_steps}
+    with env(VPLBM_TWO_STEP=int(two_step), VPLBM_LOG=1, **extra):
         s = gpu_sim(case, storage=storage, device_mask=ids is None)
         if ids is not None:
             s.set_mask(ids, case.bodies)
@@ -72,8 +73,8 @@ def test_two_step_bitwise_equals_one_step(gpu, capfd, spec, storage):
     1 and 3 more: bitwise the same populations as one step per launch."""
     case, ids = build_case(*spec, seed=11)
     fields = I.random_fields(case.nx, case.ny, 11, u_mean=case.u_in)
-    a = make(case, ids, storage, fields, True, capfd)
-    b = make(case, ids, storage, fields, False, capfd)
+    a = make(case, ids, storage, fields, True, capfd, graph_steps=32)
+    b = make(case, ids, storage, fields, False, capfd, graph_steps=32)
     done = 0
     for n in (101, 1, 3):
         a.step(n)
@@ -91,8 +92,8 @@ def test_two_step_ring_and_restart(gpu):
     spec = CASES[2]                                           # channel with two disks
     case, ids = build_case(*spec, seed=21)
     fields = I.random_fields(case.nx, case.ny, 21, u_mean=case.u_in)
-    a = make(case, ids, "f64", fields, True)
-    b = make(case, ids, "f64", fields, False)
+    a = make(case, ids, "f64", fields, True, graph_steps=32)
+    b = make(case, ids, "f64", fields, False, graph_steps=32)
     done = 0
     for n in (2, 1, 2, 64, 5, 33, 4):
         a.step(n)
@@ -113,10 +114,10 @@ def test_two_step_ring_and_restart(gpu):
 
 @pytest.mark.parametrize("nx,ny,storage,steps", [
     (2048, 512, "f32", 200),
-    (8192, 2048, "f16s", 64),
-    (8192, 2048, "f32", 64),
+    (8192, 2048, "f16s", 130),
+    (8192, 2048, "f32", 130),
     (2100, 2001, "bf16sr", 21),
-    (6048, 2016, "f32", 65),
+    (6048, 2016, "f32", 131),
     (2048, 512, "f32", 20000),
     (2048, 512, "f16sr", 20000),
 ], ids=["wake_2048x512_f32", "wake_8192x2048_f16s", "wake_8192x2048_f32", "ragged_tall_tiles_bf16sr",
@@ -185,8 +186,8 @@ def test_bodies_start_moving_mid_run(gpu):
     case = I.cylinder_wake(300, 120, d=20.0, x0=80.0, re=100.0, storage="f32")
     moving = [dict(b, ax=0.0, ay=4.0, freq=0.01) for b in case.bodies]
     fields = I.random_fields(case.nx, case.ny, 8, u_mean=case.u_in)
-    a = make(case, None, "f32", fields, True)
-    b = make(case, None, "f32", fields, False)
+    a = make(case, None, "f32", fields, True, graph_steps=32)
+    b = make(case, None, "f32", fields, False, graph_steps=32)
     for s in (a, b):
         s.step(33)
         s.set_mask(None, moving)
