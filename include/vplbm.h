@@ -131,8 +131,9 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
 
 /* Advance nsteps >= 0 steps (asynchronous on the stream).  Pairs of steps share one kernel launch
    (the first kept on chip; see vplbm_steps_per_launch), an odd last step takes its own, and chunks
-   of steps are replayed from a captured HIP graph.  Returns VPLBM_EUNSTABLE if an earlier
-   vplbm_observables saw status 1. */
+   of 128 steps are replayed from a captured HIP graph (the environment variable
+   VPLBM_GRAPH_STEPS at create sets another even chunk; 0 launches every step directly).  Returns
+   VPLBM_EUNSTABLE if an earlier vplbm_observables saw status 1. */
 int vplbm_step(vplbm_sim s, int64_t nsteps);
 
 /* Observables of the last executed step; if rho/ux/uy are not NULL they receive (host, nx*ny,
