@@ -138,13 +138,22 @@ __device__ __forceinline__ unsigned xorshift32(unsigned x)
 // binary16 quantum is 2^-24: scale, add a uniform fraction, take the floor, scale back (all exact).
 // Above, add the random bits under the 10 kept mantissa bits of the binary32 pattern and drop them
 // (a carry moves into the exponent as it should); the result is exact in binary16.
+__device__ __forceinline__ bool f16_sr_tiny(float v) { return __builtin_fabsf(v) < 6.103515625e-05f; }
+
+__device__ __forceinline__ _Float16 f16_sr_below(float v, unsigned r)   // |v| < 2^-14
+{
+    const float n = __builtin_floorf(v * 16777216.0f + float(r & 0x1FFFu) * 1.220703125e-04f);
+    return (_Float16)(n * 5.9604644775390625e-08f);
+}
+
+__device__ __forceinline__ _Float16 f16_sr_above(float v, unsigned r)   // |v| >= 2^-14
+{
+    return (_Float16)__uint_as_float((__float_as_uint(v) + (r & 0x1FFFu)) & ~0x1FFFu);
+}
+
 __device__ __forceinline__ _Float16 f16_stochastic(float v, unsigned r)
 {
-    if (__builtin_fabsf(v) < 6.103515625e-05f) {
-        const float n = __builtin_floorf(v * 16777216.0f + float(r & 0x1FFFu) * 1.220703125e-04f);
-        return (_Float16)(n * 5.9604644775390625e-08f);
-    }
-    return (_Float16)__uint_as_float((__float_as_uint(v) + (r & 0x1FFFu)) & ~0x1FFFu);
+    return f16_sr_tiny(v) ? f16_sr_below(v, r) : f16_sr_above(v, r);
 }
 
 // bfloat16 (the top 16 bits of binary32) with stochastic rounding; r holds 16 random bits.
@@ -155,6 +164,11 @@ __device__ __forceinline__ unsigned short bf16_stochastic_bits(float v, unsigned
 
 template <> struct Codec<kF16SR> : Codec<kF16S> {
     static constexpr bool stochastic = true;
+    static __device__ __forceinline__ void store_raw(elem *p, unsigned i, _Float16 q) { *at(p, i) = q; }
+    static __device__ __forceinline__ void store_raw_nt(elem *p, unsigned i, _Float16 q)
+    {
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, q), reinterpret_cast<unsigned short *>(at(p, i)));
+    }
     static __device__ __forceinline__ void store_sr(elem *p, unsigned i, real h, unsigned r) { *at(p, i) = f16_stochastic(h, r); }
     static __device__ __forceinline__ void store_sr_nt(elem *p, unsigned i, real h, unsigned r)
     {
@@ -540,7 +554,34 @@ __device__ __forceinline__ void store_node(typename Codec<S>::elem *__restrict__
 {
     using C = Codec<S>;
     using T = typename C::real;
-    if constexpr (C::stochastic) {
+    if constexpr (S == kF16SR) {
+        // As below, with the values under 2^-14 (rare: solid nodes at rest) redone in a
+        // wave-uniform branch that only waves holding such a value take.  Selected per lane, their
+        // exact-quantum rounding cost every stored value its instructions.  Same results.
+        const unsigned r0 = mix32(node ^ mix32(step * 0x9e3779b9u + 0x7f4a7c15u));
+        unsigned r = r0;
+        _Float16 q[9];
+        bool tiny = false;
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            if (k % 2 == 0 && k > 0) r = xorshift32(r);
+            q[k] = f16_sr_above(f[k], (k % 2) ? (r >> 16) : r);
+            tiny |= f16_sr_tiny(f[k]);
+        }
+        if (__any(tiny)) {
+            r = r0;
+#pragma unroll
+            for (int k = 0; k < 9; k++) {
+                if (k % 2 == 0 && k > 0) r = xorshift32(r);
+                if (f16_sr_tiny(f[k])) q[k] = f16_sr_below(f[k], (k % 2) ? (r >> 16) : r);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            if (NT) C::store_raw_nt(dst + k * plane, i, q[k]);
+            else C::store_raw(dst + k * plane, i, q[k]);
+        }
+    } else if constexpr (C::stochastic) {
         // one hash per node and step, then two 16-bit words per xorshift state
         unsigned r = mix32(node ^ mix32(step * 0x9e3779b9u + 0x7f4a7c15u));
 #pragma unroll
