@@ -95,3 +95,36 @@ def test_stochastic_rounding_is_unbiased(gpu, storage, mant):
         two_valued += len(np.unique(got[k])) == 2
         assert abs(d.mean()) <= max(5 * u * 0.5 / np.sqrt(d.size), 1e-12 * abs(w[0]))
     assert two_valued >= 7
+
+
+def test_f16sr_rounds_subnormal_values_on_their_quantum(gpu):
+    """Fluid at rest with density 1 + 1e-4: every shifted population h = w (rho - 1) lies below
+    2^-14, in binary16's subnormal range, where the quantum is 2^-24 and FP16SR takes its separate
+    exact-quantum rounding (a branch that only waves holding such values take).  Each stored h must
+    be one of the two multiples of 2^-24 around the FP32 value, both must occur (in most planes: a
+    value very close to a multiple may round the same way at every node), and their mean over the
+    16384 nodes must be within 5 standard errors of it."""
+    q = 2.0 ** -24
+    case = I.Case("sr_rest", 128, 128, storage="f16sr", bc=I.ALL_PERIODIC, u0=(0.0, 0.0),
+                  rho0=1.0 + 1e-4, tau=0.7)
+    g = gpu_sim(case)
+    start = g.populations()
+    ref = gpu_sim(case, storage="f32")
+    ref.set_populations(start, 0)
+    g.step(1)
+    ref.step(1)
+    got, want = g.populations(), ref.populations()
+    two_valued = 0
+    for k in range(9):
+        w = want[k].ravel()
+        assert np.ptp(w) == 0.0
+        h_ref = w[0] - W[k]
+        assert 0.0 < abs(h_ref) < 2.0 ** -14
+        h = got[k].ravel() - W[k]
+        n = h / q
+        assert np.all(np.abs(n - np.round(n)) < 1e-6)              # on the subnormal grid
+        lo, hi = np.floor(h_ref / q) * q, np.ceil(h_ref / q) * q
+        assert np.all((np.abs(h - lo) < 1e-3 * q) | (np.abs(h - hi) < 1e-3 * q))
+        two_valued += len(np.unique(got[k])) == 2
+        assert abs(h.mean() - h_ref) <= 5 * q * 0.5 / np.sqrt(h.size)
+    assert two_valued >= 6
