@@ -4,14 +4,17 @@
 
 A "step" is one lattice update of the whole grid: pull-streaming, edge rules, mask fetch,
 moments, penalization, collision, store, and the FP64 mass/force reductions.  The default
-workload is the 2048 x 512 cylinder wake (VP-MRT, FP32 storage, Zou-He inlet, outflow, free-slip
-walls, disk D = 64, Re = 200).  Its mask is static, so the library runs two steps per launch
-(the intermediate step kept in LDS); `one_step_per_launch` times the same workload with one step
-per launch, the memory-bound kernel.  The two population buffers (75 MB) fit in the 256 MB
-Infinity Cache, so the line also carries `hbm_resident`: the 8192 x 2048 oscillating-cylinder
-workload (FP32, mask rebuilt on the device every step), whose buffers (1.2 GB) do not, with and
-without two steps per launch, `reduced_precision`: the 8192 x 2048 cylinder in every storage
-format, and `paper_cylinder_re500`: the paper's 6048 x 2016 Re = 500 case (convective outlet).
+workload is the 8192 x 2048 transversely oscillating cylinder (VP-MRT, FP32 storage, Zou-He
+inlet, outflow, free-slip walls, disk D = 96, Re = 300, mask and solid velocity rebuilt on the
+device every step).  Its two population buffers (1.2 GB) far exceed the 256 MB Infinity Cache, so
+the step streams from HBM and the line's `roofline` is an HBM figure.  The library runs two steps
+per launch (the intermediate step kept in LDS); `one_step_per_launch` times the same workload with
+one step per launch, the memory-bound kernel.  Beside it the line carries `cache_resident` (the
+2048 x 512 cylinder wake, whose 75 MB of buffers fit in the cache: MLUPS only),
+`taylor_couette_128` (the 128 x 128 FP64 case, launch-bound: MLUPS only), `reduced_precision`
+(the 8192 x 2048 cylinder in every storage format), `paper_cylinder_re500` (the paper's
+6048 x 2016 Re = 500 case with its convective outlet), a square FP32 sweep, the measured copy
+ceiling, the serving workload and the FP64 oracle on the host's cores (`cpu_baseline`).
 
 Prints one JSON line.  Inputs are synthetic (seeded geometry, uniform start) and resident on the
 GPU before timing starts.  `--copy-probe BYTES` instead times a plain device copy (the measured
@@ -42,6 +45,12 @@ def source_digest():
         with open(os.path.join(ROOT, "paper_1812_05401_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def cache_resident(case):
+    """Whether the two population buffers fit in the 256 MB Infinity Cache."""
+    eb = {"f64": 8, "f32": 4, "f32d": 4}.get(case.storage, 2)
+    return case.nx * case.ny * 2 * 9 * eb < 256e6
 
 
 def profile_entry(table, workload, storage, steps_per_launch):
@@ -105,17 +114,25 @@ def time_workload(case, steps, warmup, storage=None, two_step=True):
         raise RuntimeError(f"{case.name}: unstable")
     bpu = B.vplbm_bytes_per_update(case.storage)
     # One launch updates every node spl times (the graph's step-counter kernel, one per 128 steps,
-    # is noise).  Its algorithmic bytes are one read and one write of the planes plus the mask
-    # whatever spl is: the two-step kernel keeps the intermediate step on chip.
+    # and, with moving bodies, the kernel that rebuilds their masks before each launch are included
+    # in the launch time).  The bytes it moves are one read and one write of the planes plus the
+    # mask whatever spl is: the two-step kernel keeps the intermediate step on chip.
     launch_s = gpu_ms / 1e3 / steps * spl
     # moving bodies: a two-step launch reads the masks of both of its steps (1 B per node more)
     moving = any(b["freq"] != 0 and (b["ax"] != 0 or b["ay"] != 0) for b in case.bodies)
     bytes_launch = (bpu + (1 if spl == 2 and moving else 0)) * case.nodes
     hbm = bytes_launch / launch_s / 1e9
+    # The per-update figure: bpu bytes (9 loads, 9 stores, the mask) for each of the spl lattice
+    # updates of a launch, over the same launch time.  Above 1 for the two-step kernel, which
+    # moves those bytes once per two updates.
+    per_update = bpu * spl * case.nodes / launch_s / 1e9
     kernel = "vplbm::step2_kernel" if spl == 2 else "vplbm::step_kernel"
     roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(hbm / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(case.name, case.storage, spl),
+            "frac_per_update_bytes": round(per_update / HBM_PEAK_GBS, 4),
+            "achieved_per_update_bytes": round(per_update, 1),
+            "bytes_per_update": bpu,
             "kernel": kernel, "lattice_updates_per_launch": spl, "launch_us": round(launch_s * 1e6, 3),
             "bytes_per_launch": bytes_launch, "bytes_per_node_per_launch": bytes_launch // case.nodes}
     valu = profile_entry("valu", case.name, case.storage, spl)
@@ -137,13 +154,37 @@ def time_workload(case, steps, warmup, storage=None, two_step=True):
     }
 
 
-def cpu_baseline(case, steps):
+def host_threads():
+    """Threads the oracle may use: the processors this process may run on, at most the
+    OMP_NUM_THREADS the environment sets (a GPU machine's CPU share)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(n, 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_mlups(case, steps, threads):
+    """The FP64 oracle (test infrastructure, not the product path) on `steps` steps of `case`:
+    MLUPS over the step loop alone, every node counted."""
     import oracle as O
     kinds = {"disk": O.DISK, "rect": O.RECT, "disk_outside": O.DISK_OUTSIDE}
     bcs = {"periodic": O.PERIODIC, "velocity": O.VELOCITY, "outflow": O.OUTFLOW,
-           "freeslip": O.FREESLIP}
+           "freeslip": O.FREESLIP, "convective": O.CONVECTIVE}
     s = O.OracleSim(case.nx, case.ny, O.MRT if case.collision == "mrt" else O.SRT, tau=case.tau,
-                    lam=case.lam, eta=case.eta, bc=tuple(bcs[b] for b in case.bc), u_in=case.u_in)
+                    lam=case.lam, eta=case.eta, bc=tuple(bcs[b] for b in case.bc), u_in=case.u_in,
+                    threads=threads)
     s.set_bodies([O.make_body(kinds[b["kind"]], b["cx"], b["cy"], b["r"], b["hx"], b["hy"],
                               b["ux"], b["uy"], b["omega"], b["ax"], b["ay"], b["freq"])
                   for b in case.bodies])
@@ -151,10 +192,36 @@ def cpu_baseline(case, steps):
     t0 = time.perf_counter()
     s.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": round(case.nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} steps of {case.name} ({case.nodes} nodes), FP64 oracle, "
-                      f"{case.collision.upper()} in moment space, one thread, {dt:.1f} s"}
+    used = s.threads
+    s.close()
+    return {"workload": case.name, "nodes": case.nodes, "collision": case.collision,
+            "steps": steps, "threads": used, "seconds": round(dt, 3),
+            "mlups": round(case.nodes * steps / dt / 1e6, 3)}
+
+
+def cpu_baseline(head, samples):
+    """The FP64 oracle timed on the host: one thread and every thread this process may use, on a
+    bounded sample of the headline workload and of the other workloads in `samples` [(case,
+    steps_one_thread, steps_all_threads)].  The thread count does not change the oracle's
+    results (its per-step sums are serial)."""
+    nthr = host_threads()
+    legs = []
+    for case, s1, sn in samples:
+        for th, n in ((1, s1), (nthr, sn)):
+            r = oracle_mlups(case, n, th)
+            legs.append(r)
+            print(f"# cpu oracle {case.name}: {r['threads']} thread(s), {n} steps, "
+                  f"{r['mlups']:.2f} MLUPS", file=sys.stderr, flush=True)
+    main = [r for r in legs if r["workload"] == head.name]
+    one = next(r for r in main if r["threads"] == 1)
+    allc = next(r for r in main if r["threads"] != 1) if nthr > 1 else one
+    return {"value": allc["mlups"], "unit": "MLUPS", "cores": allc["threads"], "kind": "oracle",
+            "sample": f"{allc['steps']} steps of {head.name} ({head.nodes} nodes), FP64 oracle, "
+                      f"{head.collision.upper()} in moment space, {allc['threads']} threads, "
+                      f"{allc['seconds']:.1f} s; one thread: {one['steps']} steps, "
+                      f"{one['mlups']:.2f} MLUPS",
+            "threads_1": one, "threads_all": allc, "nproc": os.cpu_count(),
+            "threads_available": nthr, "cpu_model": cpu_model(), "legs": legs}
 
 
 def serving_leg(n_requests, loads, budget_bytes, fifo_loads):
@@ -238,12 +305,12 @@ def copy_probe(nbytes, reps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6144)     # 48 graph replays of 128 steps
-    ap.add_argument("--warmup", type=int, default=768)
-    ap.add_argument("--workload", default="cylinder_wake_2048x512")
+    ap.add_argument("--steps", type=int, default=1024)     # 8 graph replays of 128 steps
+    ap.add_argument("--warmup", type=int, default=128)
+    ap.add_argument("--workload", default="oscillating_cylinder_8192x2048")
     ap.add_argument("--storage", default="", help="storage format of the workload (default: its own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 8192 x 2048 objects")
+    ap.add_argument("--no-extra", action="store_true", help="skip the objects beside the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--precision-study", default="", metavar="WORKLOAD",
@@ -335,8 +402,10 @@ def main():
         "config": {"workload": case.name, "nx": case.nx, "ny": case.ny,
                    "collision": case.collision, "storage": case.storage, "tau": case.tau,
                    "lambda": case.lam, "eta": case.eta, "bc": list(case.bc),
-                   "bodies": len(case.bodies), "reductions": "fp64 mass + body force, every step",
-                   "cache_resident": case.nx * case.ny * 2 * 9 * {"f64": 8, "f32": 4}.get(case.storage, 2) < 256e6},
+                   "bodies": len(case.bodies),
+                   "moving_bodies": any(b["freq"] != 0 for b in case.bodies),
+                   "reductions": "fp64 mass + body force, every step",
+                   "cache_resident": cache_resident(case)},
         "roofline": main_res["roofline"],
         "steps_per_launch": main_res["steps_per_launch"],
         "one_step_equivalent_gbs": main_res["one_step_equivalent_gbs"],
@@ -348,14 +417,22 @@ def main():
         line["one_step_per_launch"] = {k: one[k] for k in ("mlups", "ms_per_step", "roofline")}
         print(f"# {case.name} one step per launch: {one['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     if not args.no_extra:
-        big = I.oscillating_cylinder_8192x2048()
-        r = time_workload(big, 400, 40)
-        line["hbm_resident"] = {k: r[k] for k in ("workload", "storage", "mlups", "ms_per_step",
-                                                  "steps_per_launch", "roofline")}
-        print(f"# {big.name}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        r1 = time_workload(I.oscillating_cylinder_8192x2048(), 400, 40, two_step=False)
-        line["hbm_resident"]["one_step_per_launch"] = {k: r1[k] for k in ("mlups", "ms_per_step", "roofline")}
-        print(f"# {big.name} one step per launch: {r1['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        # the 2048 x 512 wake: buffers inside the Infinity Cache, so MLUPS only
+        c2 = I.cylinder_wake_2048x512()
+        r = time_workload(c2, 6144, 768)
+        line["cache_resident"] = {"workload": c2.name, "storage": c2.storage, "steps": 6144,
+                                  "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
+                                  "steps_per_launch": r["steps_per_launch"],
+                                  "note": "75 MB of buffers inside the 256 MB Infinity Cache: MLUPS only"}
+        print(f"# {c2.name}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        # the 128 x 128 FP64 Taylor-Couette case over its 5000 steps: launch-bound, MLUPS only
+        c1 = I.taylor_couette_128()
+        r = time_workload(c1, 5000, 200)
+        line["taylor_couette_128"] = {"workload": c1.name, "storage": c1.storage, "steps": 5000,
+                                      "mlups": round(r["mlups"], 1), "ms_per_step": r["ms_per_step"],
+                                      "steps_per_launch": r["steps_per_launch"],
+                                      "note": "16,384 nodes: launch-bound, MLUPS only"}
+        print(f"# {c1.name}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         red = {}
         for st in ("f64", "f32", "f32d", "f16s", "f16sr", "bf16s", "bf16sr"):
             c = I.cylinder_wake_8192x2048(st)
@@ -385,16 +462,18 @@ def main():
         line["square_sweep_f32"] = sweep
         cp = measure_copy(1 << 30, 20)
         line["copy_probe"] = cp
-        for obj in [line["roofline"], line["hbm_resident"]["roofline"],
-                    line["hbm_resident"]["one_step_per_launch"]["roofline"],
-                    line.get("one_step_per_launch", {}).get("roofline")]:
+        for obj in [line["roofline"], line.get("one_step_per_launch", {}).get("roofline")]:
             if not obj:
                 continue
             obj["frac_of_copy"] = round(obj["achieved"] / cp["gbs_read_plus_write"], 4)
     if not args.no_serving:
         line["serving"] = serving_leg(args.serving_requests, (0.7, 1.2), 2 << 30, (0.7, 1.2))
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(I.cylinder_wake_2048x512(), 100)
+        # bounded samples (about 20 s of oracle work on a 16-thread share): the headline workload,
+        # the 2048 x 512 wake and the whole 5000-step 128 x 128 Taylor-Couette run
+        line["cpu_baseline"] = cpu_baseline(case, [(workloads[args.workload](), 2, 12),
+                                                   (I.cylinder_wake_2048x512(), 30, 300),
+                                                   (I.taylor_couette_128(), 5000, 5000)])
     print(json.dumps(line), flush=True)
 
 

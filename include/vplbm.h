@@ -111,7 +111,8 @@ typedef struct {
     double fx[VPLBM_MAX_BODIES]; /* force of the fluid on body k: minus the sum of the     */
     double fy[VPLBM_MAX_BODIES]; /* penalization force over the body's nodes in that step  */
     int32_t nbodies;
-    int32_t status;              /* 0 ok, 1 unstable (non-finite or non-positive density seen) */
+    int32_t status;              /* 0 ok, 1 unstable (non-finite or non-positive density seen);
+                                    pool requests: 2 = device memory refused (VPLBM_FAILED) */
 } vplbm_obs;
 
 typedef struct vplbm_sim_s *vplbm_sim;
@@ -216,7 +217,9 @@ enum vplbm_request_state {
     VPLBM_QUEUED = 0,    /* submitted, waiting for memory or a slot */
     VPLBM_RUNNING = 1,   /* resident, advancing */
     VPLBM_DONE = 2,      /* finished; results held until vplbm_pool_result */
-    VPLBM_FAILED = 3,    /* became unstable; results hold the last observables */
+    VPLBM_FAILED = 3,    /* became unstable (status 1; results hold the last observables), or
+                            the device refused its memory while nothing else was resident
+                            (status 2; no step done, no fields) */
     VPLBM_CANCELLED = 4  /* cancelled; results hold the steps done (and the fields if kept) */
 };
 

@@ -76,6 +76,10 @@ def lib():
         L.orc_get_populations.argtypes = [C.c_void_p, dp]
         L.orc_pull_node.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp]
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_set_threads.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_set_threads.restype = C.c_int
+        L.orc_get_threads.argtypes = [C.c_void_p]
+        L.orc_get_threads.restype = C.c_int32
         L.orc_steps_done.argtypes = [C.c_void_p]
         L.orc_steps_done.restype = C.c_int64
         L.orc_get_obs.argtypes = [C.c_void_p, C.POINTER(Obs)]
@@ -186,7 +190,8 @@ class OracleSim:
     step, observe) so tests can drive both the same way."""
 
     def __init__(self, nx, ny, collision=SRT, tau=0.8, lam=3.0 / 16.0, eta=1e-7,
-                 bc=(PERIODIC, PERIODIC, PERIODIC, PERIODIC), u_in=(0.0, 0.0), rates=None):
+                 bc=(PERIODIC, PERIODIC, PERIODIC, PERIODIC), u_in=(0.0, 0.0), rates=None,
+                 threads=1):
         cfg = Config()
         cfg.nx, cfg.ny, cfg.collision = nx, ny, collision
         cfg.tau, cfg.lambda_, cfg.eta = tau, lam, eta
@@ -202,6 +207,19 @@ class OracleSim:
         self.h = h
         self.nx, self.ny = nx, ny
         self.nbodies = 0
+        self.set_threads(threads)
+
+    def set_threads(self, n):
+        """OpenMP threads for the node loops (0: every processor); the results are bitwise the
+        same for every count.  Returns the count in use."""
+        got = lib().orc_set_threads(self.h, int(n))
+        if got < 0:
+            raise ValueError("thread count must be >= 0")
+        return got
+
+    @property
+    def threads(self):
+        return lib().orc_get_threads(self.h)
 
     def close(self):
         if self.h:

@@ -10,6 +10,11 @@
  * Only tests, the smoke check and the CPU-baseline leg of the benchmark use this file.  It shares
  * nothing with the GPU library.
  *
+ * Threads.  A step's node updates are independent (each reads the previous state and writes its
+ * own node), so orc_step may hand rows to OpenMP threads (orc_set_threads).  Each node's arithmetic
+ * is the same whichever thread does it, and the per-step sums (mass, body forces) are added by one
+ * thread in row-major order afterwards, so every thread count gives bitwise the one-thread result.
+ *
  * Readings taken where the paper is silent (each is listed in the design notes):
  *   R1 stored state = post-collision g; a step pulls g into f, applies edges, then collides.
  *   R2 Eqs. 17-18 are evaluated in the algebraically equal, well-conditioned form
@@ -35,6 +40,7 @@
 #include "vplbm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -286,6 +292,9 @@ struct orc_sim {
     int64_t n;              /* steps done */
     orc_obs obs;
     double *prev, *prevn;   /* convective outlet: last column's unknowns 3, 6, 7 ([3][ny]) */
+    double *rho_n;          /* per node of the step in progress: density and penalization force, */
+    double *fpx_n, *fpy_n;  /*   summed in row-major order once every node is done */
+    int threads;            /* OpenMP threads for the node loops (1: none) */
 };
 
 static const int OUTLET_DIRS[3] = {3, 6, 7};   /* populations entering from x = nx */
@@ -323,6 +332,10 @@ orc_sim *orc_create(const orc_config *cfg)
     s->ids = (uint8_t *)calloc(N, 1);
     s->prev = (double *)calloc(3 * (size_t)cfg->ny, sizeof(double));
     s->prevn = (double *)calloc(3 * (size_t)cfg->ny, sizeof(double));
+    s->rho_n = (double *)calloc(N, sizeof(double));
+    s->fpx_n = (double *)calloc(N, sizeof(double));
+    s->fpy_n = (double *)calloc(N, sizeof(double));
+    s->threads = 1;
     s->n = 0;
     s->obs.step = -1;
     return s;
@@ -336,8 +349,20 @@ void orc_destroy(orc_sim *s)
     free(s->ids);
     free(s->prev);
     free(s->prevn);
+    free(s->rho_n);
+    free(s->fpx_n);
+    free(s->fpy_n);
     free(s);
 }
+
+int orc_set_threads(orc_sim *s, int32_t threads)
+{
+    if (threads < 0) return -1;
+    s->threads = threads ? threads : omp_get_max_threads();
+    return s->threads;
+}
+
+int32_t orc_get_threads(const orc_sim *s) { return s->threads; }
 
 /* Reading R5: node-centre inclusion, lowest-index body wins. */
 static void rasterize(orc_sim *s, double t)
@@ -345,6 +370,7 @@ static void rasterize(orc_sim *s, double t)
     int nx = s->cfg.nx, ny = s->cfg.ny;
     double c[ORC_MAX_BODIES][2], v[ORC_MAX_BODIES][2];
     for (int k = 0; k < s->nb; k++) orc_body_state(&s->bodies[k], t, c[k], v[k]);
+#pragma omp parallel for schedule(static) num_threads(s->threads)
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
             uint8_t id = 0;
@@ -509,10 +535,8 @@ void orc_step(orc_sim *s, int64_t nsteps)
     for (int64_t it = 0; it < nsteps; it++) {
         double t = (double)s->n;
         if (s->rasterize && s->moving) rasterize(s, t);
-        nsum mass = {0, 0}, fx[ORC_MAX_BODIES], fy[ORC_MAX_BODIES], fa[ORC_MAX_BODIES];
-        memset(fx, 0, sizeof(fx));
-        memset(fy, 0, sizeof(fy));
-        memset(fa, 0, sizeof(fa));
+        /* every node: stream, edges, moments, penalization, collision (rows may go to threads) */
+#pragma omp parallel for schedule(static) num_threads(s->threads)
         for (int y = 0; y < ny; y++)
             for (int x = 0; x < nx; x++) {
                 double f[9], rho, u[2], fpen[2], out[9];
@@ -524,13 +548,24 @@ void orc_step(orc_sim *s, int64_t nsteps)
                 for (int a = 0; a < 9; a++) s->gn[a * N + i] = out[a];
                 if (x == nx - 1)
                     for (int k = 0; k < 3; k++) s->prevn[k * ny + y] = f[OUTLET_DIRS[k]];
-                nadd(&mass, rho);
-                if (id) {
-                    nadd(&fx[id - 1], -fpen[0]);
-                    nadd(&fy[id - 1], -fpen[1]);
-                    nadd(&fa[id - 1], fabs(fpen[0]) + fabs(fpen[1]));
-                }
+                s->rho_n[i] = rho;
+                s->fpx_n[i] = fpen[0];
+                s->fpy_n[i] = fpen[1];
             }
+        /* the step's sums, one thread, row-major order */
+        nsum mass = {0, 0}, fx[ORC_MAX_BODIES], fy[ORC_MAX_BODIES], fa[ORC_MAX_BODIES];
+        memset(fx, 0, sizeof(fx));
+        memset(fy, 0, sizeof(fy));
+        memset(fa, 0, sizeof(fa));
+        for (size_t i = 0; i < N; i++) {
+            nadd(&mass, s->rho_n[i]);
+            int id = s->ids[i];
+            if (id) {
+                nadd(&fx[id - 1], -s->fpx_n[i]);
+                nadd(&fy[id - 1], -s->fpy_n[i]);
+                nadd(&fa[id - 1], fabs(s->fpx_n[i]) + fabs(s->fpy_n[i]));
+            }
+        }
         double *tmp = s->g; s->g = s->gn; s->gn = tmp;
         tmp = s->prev; s->prev = s->prevn; s->prevn = tmp;
         s->obs.step = s->n;
@@ -554,6 +589,7 @@ void orc_get_fields(orc_sim *s, double *rho, double *ux, double *uy)
     int nx = s->cfg.nx, ny = s->cfg.ny;
     double t = (double)s->n;
     if (s->rasterize && s->moving) rasterize(s, t);
+#pragma omp parallel for schedule(static) num_threads(s->threads)
     for (int y = 0; y < ny; y++)
         for (int x = 0; x < nx; x++) {
             double f[9], r, u[2], fpen[2];

@@ -90,6 +90,13 @@ void orc_set_populations(orc_sim *s, const double *pop);
 void orc_get_populations(const orc_sim *s, double *pop);
 void orc_pull_node(const orc_sim *s, int32_t x, int32_t y, double f[9]); /* streamed + edges */
 void orc_step(orc_sim *s, int64_t nsteps);
+/* OpenMP threads for the node loops of orc_step, orc_get_fields and the mask rasterization
+   (default 1; 0 = OpenMP's default: OMP_NUM_THREADS if set, else every processor).  Results
+   are bitwise the same for every count: each node's arithmetic does not depend on the thread,
+   and the per-step sums are added afterwards by one thread in row-major order.  Returns the
+   count now in use, or -1 for a negative argument. */
+int orc_set_threads(orc_sim *s, int32_t threads);
+int32_t orc_get_threads(const orc_sim *s);
 int64_t orc_steps_done(const orc_sim *s);
 void orc_get_obs(const orc_sim *s, orc_obs *out);
 void orc_get_fields(orc_sim *s, double *rho, double *ux, double *uy);

@@ -654,15 +654,12 @@ hipError_t launch_outlet_init(int storage, const StepArgs &a, void *prev, hipStr
 
 // ---- obstacles ---------------------------------------------------------------------------------
 
-__global__ void bodies_kernel(const BodyParams *p, BodyState *s, int nb, const long long *t_base,
-                              int t_off)
+// State of a body at time t: centre c0 + a sin(2 pi f t), velocity U + 2 pi f a cos(2 pi f t).
+// FP64 without contraction; every kernel that places bodies uses this one function.
+__device__ __forceinline__ BodyState body_state_at(const BodyParams &b, double t)
 {
 #pragma clang fp contract(off)
-    const int k = threadIdx.x;
-    if (k >= nb) return;
-    const double t = double(*t_base + t_off);
     const double two_pi = 6.283185307179586;
-    const BodyParams b = p[k];
     const double ph = two_pi * b.freq * t;
     const double sn = sin(ph), cs = cos(ph);
     BodyState o;
@@ -671,20 +668,15 @@ __global__ void bodies_kernel(const BodyParams *p, BodyState *s, int nb, const l
     o.vx = b.ux + b.ax * two_pi * b.freq * cs;
     o.vy = b.uy + b.ay * two_pi * b.freq * cs;
     o.omega = b.omega;
-    s[k] = o;
+    return o;
 }
 
-// Node-centre inclusion in FP64 without contraction, so that the decision for a node is the
-// correctly rounded one: the lowest-index body containing the node owns it.
-__global__ __launch_bounds__(kBlock) void mask_kernel(uint8_t *mask, Geom g, const BodyParams *p,
-                                                      const BodyState *s, int nb, int x0, int y0,
-                                                      int w, int h)
+// Body id of node (x, y): node-centre inclusion in FP64 without contraction, so that the decision
+// is the correctly rounded one; the lowest-index body containing the node owns it.
+__device__ __forceinline__ uint8_t rasterize_node(int x, int y, const BodyParams *p,
+                                                  const BodyState *s, int nb)
 {
 #pragma clang fp contract(off)
-    const int node = blockIdx.x * kBlock + threadIdx.x;
-    if (node >= w * h) return;
-    const int x = x0 + node % w, y = y0 + node / w;
-    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) return;
     int id = 0;
     for (int k = 0; k < nb && id == 0; k++) {
         const double dx = double(x) - s[k].cx, dy = double(y) - s[k].cy;
@@ -696,13 +688,77 @@ __global__ __launch_bounds__(kBlock) void mask_kernel(uint8_t *mask, Geom g, con
         else inside = d2 >= r2;
         if (inside) id = k + 1;
     }
-    mask[y * g.pitch + x] = (uint8_t)id;
+    return (uint8_t)id;
+}
+
+__global__ void bodies_kernel(const BodyParams *p, BodyState *s, int nb, const long long *t_base,
+                              int t_off)
+{
+    const int k = threadIdx.x;
+    if (k >= nb) return;
+    s[k] = body_state_at(p[k], double(*t_base + t_off));
+}
+
+__global__ __launch_bounds__(kBlock) void mask_kernel(uint8_t *mask, Geom g, const BodyParams *p,
+                                                      const BodyState *s, int nb, int x0, int y0,
+                                                      int w, int h)
+{
+    const int node = blockIdx.x * kBlock + threadIdx.x;
+    if (node >= w * h) return;
+    const int x = x0 + node % w, y = y0 + node / w;
+    if (x < 0 || x >= g.nx || y < 0 || y >= g.ny) return;
+    mask[y * g.pitch + x] = rasterize_node(x, y, p, s, nb);
+}
+
+// Moving bodies before a launch of a.nsteps (1 or 2) steps: for each step s, the body states at
+// time *t_base + t_off + s into a.state[s] and the swept boxes of the moving bodies re-rasterized
+// into a.mask[s], in one launch.  Every workgroup computes the states it needs into LDS (a few
+// FP64 sines per body); workgroup 0 also stores them.  The box nodes of all steps are spread over
+// the grid.  Boxes may overlap: such a node is written more than once with the same id.
+__global__ __launch_bounds__(kBlock) void place_kernel(PlaceArgs a)
+{
+    __shared__ BodyState st[2][kMaxBodies];
+    __shared__ BodyParams bp[kMaxBodies];
+    const int nb = a.nbodies;
+    if ((int)threadIdx.x < nb) bp[threadIdx.x] = a.params[threadIdx.x];
+    __syncthreads();
+    if ((int)threadIdx.x < a.nsteps * nb) {
+        const int sidx = threadIdx.x / nb, k = threadIdx.x % nb;
+        const BodyState o = body_state_at(bp[k], double(*a.t_base + a.t_off + sidx));
+        st[sidx][k] = o;
+        if (blockIdx.x == 0) a.state[sidx][k] = o;
+    }
+    __syncthreads();
+    const int total = a.box_start[kMaxBodies];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < a.nsteps * total; i += gridDim.x * kBlock) {
+        const int sidx = i / total, j = i % total;
+        int k = 0;
+        while (j >= a.box_start[k + 1]) k++;
+        const int* b = a.box[k];
+        const int e = j - a.box_start[k];
+        const int x = b[0] + e % b[2], y = b[1] + e / b[2];
+        a.mask[sidx][y * a.g.pitch + x] = rasterize_node(x, y, bp, st[sidx], nb);
+    }
 }
 
 hipError_t launch_bodies(const BodyParams *params, BodyState *state, int nbodies,
                          const long long *t_base, int t_off, hipStream_t st)
 {
     bodies_kernel<<<1, 64, 0, st>>>(params, state, nbodies, t_base, t_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(const PlaceArgs &a, hipStream_t st)
+{
+    const int total = a.nsteps * a.box_start[kMaxBodies];
+    if (total <= 0) {
+        // no swept box: only the states (bodies that move without changing the mask)
+        place_kernel<<<1, kBlock, 0, st>>>(a);
+        return hipGetLastError();
+    }
+    int blocks = (total + kBlock - 1) / kBlock;
+    blocks = blocks > 1024 ? 1024 : blocks;
+    place_kernel<<<blocks, kBlock, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -76,6 +76,25 @@ hipError_t launch_decode(int storage, const StepArgs &a, double *pop, hipStream_
 hipError_t launch_bodies(const BodyParams *params, BodyState *state, int nbodies,
                          const long long *t_base, int t_off, hipStream_t st);
 
+// Moving bodies before a launch of nsteps (1 or 2) steps, in one launch: for step s of the launch
+// (time *t_base + t_off + s) the body states into state[s] and the swept boxes re-rasterized into
+// mask[s].  box[k] = (x0, y0, w, h) of body k (w = 0: none, e.g. a static body); box_start holds
+// the prefix sums of the box areas (box_start[kMaxBodies] = all of them).  Every box lies inside
+// the lattice.
+struct PlaceArgs {
+    const BodyParams *params;
+    int nbodies;
+    int nsteps;
+    uint8_t *mask[2];
+    BodyState *state[2];
+    const long long *t_base;
+    int t_off;
+    Geom g;
+    int box[kMaxBodies][4];
+    int box_start[kMaxBodies + 1];
+};
+hipError_t launch_place(const PlaceArgs &a, hipStream_t st);
+
 // Rasterize the bodies into the mask over the rectangle [x0, x0+w) x [y0, y0+h).
 hipError_t launch_mask(uint8_t *mask, const Geom &g, const BodyParams *params,
                        const BodyState *state, int nbodies, int x0, int y0, int w, int h,

@@ -527,7 +527,7 @@ int retire(vplbm_pool p, int slot)
 }
 
 // Allocate and initialise a queued request in a free slot.  Returns 1 if admitted, 0 if it does
-// not fit now, < 0 on error.
+// not fit the budget now, 2 if the device refused its memory, < 0 on error.
 int admit(vplbm_pool p, Request &r, int slot)
 {
     const uint64_t nodes = (uint64_t)r.cfg.nx * r.cfg.ny;
@@ -549,7 +549,7 @@ int admit(vplbm_pool p, Request &r, int slot)
         if (hipMallocAsync(a.ptr, a.n, p->stream) != hipSuccess) {
             (void)hipGetLastError();
             free_request_memory(p, r);
-            return 0;   // the device is fuller than the budget says; retry after retirements
+            return 2;   // the device is fuller than the budget says
         }
     }
     BodyParams hp[kMaxBodies];
@@ -887,6 +887,27 @@ int vplbm_pool_advance(vplbm_pool p, int32_t *running, int32_t *queued, int32_t 
         Request &r = p->reqs[p->queue.front()];
         int rc = admit(p, r, slot);
         if (rc < 0) return rc;
+        if (rc == 2) {
+            // The device refused the memory.  With simulations resident, retirements will free
+            // some: wait.  With none, nothing ever will: the request fails instead of blocking
+            // the queue for good.
+            bool resident = false;
+            for (int s = 0; s < p->cfg.max_slots; s++) resident |= p->h_sims[s].active != 0;
+            if (!fail_when_refused(resident)) break;
+            memset(&r.obs, 0, sizeof r.obs);
+            r.obs.step = -1;
+            r.obs.nbodies = (int32_t)r.bodies.size();
+            r.obs.status = 2;
+            r.done = 0;
+            r.state = VPLBM_FAILED;
+            r.keep_fields = 0;
+            p->finished++;
+            host_log("pool %p: request %lld failed: the device refused %llu bytes with nothing resident",
+                (void *)p, (long long)r.id, (unsigned long long)r.bytes);
+            p->queue.pop_front();
+            changed = true;
+            continue;
+        }
         if (rc == 0) break;
         p->slot_req[slot] = r.id;
         p->queue.pop_front();

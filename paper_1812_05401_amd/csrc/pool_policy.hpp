@@ -26,4 +26,9 @@ inline bool may_admit(const AdmissionState &s, uint64_t bytes, uint64_t nodes)
     return true;
 }
 
+// What the pool does when the device refuses a request's memory although the budget admits it: wait
+// for retirements while simulations are resident; with none resident nothing will ever be freed,
+// so the request fails (VPLBM_FAILED, status 2) instead of blocking the queue for good.
+inline bool fail_when_refused(bool anything_resident) { return !anything_resident; }
+
 }  // namespace vplbm

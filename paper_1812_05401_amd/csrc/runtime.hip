@@ -17,6 +17,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "step_plan.hpp"
 #include "vplbm.h"
 
 using namespace vplbm;
@@ -181,24 +182,40 @@ StepArgs step_args(vplbm_sim s, int src, int t_off)
     return a;
 }
 
-// Body states and the swept part of the mask for the step at *t_dev + t_off (moving bodies),
-// into `mask` / `state` (the simulation's own, or the second step's of a two-step launch).
-hipError_t place_bodies(vplbm_sim s, int t_off, hipStream_t st, uint8_t *mask, BodyState *state)
+// Body states and the swept part of the mask for the n (1 or 2) steps at *t_dev + t_off, ...
+// (moving bodies), in one launch: step s into masks[s] / states[s] (the simulation's own, or for
+// the first step of a two-step launch the other mask and state array).
+hipError_t place_bodies_n(vplbm_sim s, int t_off, int n, hipStream_t st, uint8_t *const *masks,
+                          BodyState *const *states)
 {
-    hipError_t e = launch_bodies(s->d_params, state, s->nbodies, s->t_dev, t_off, st);
-    if (e != hipSuccess || !s->moving) return e;
-    for (int k = 0; k < s->nbodies; k++) {
-        const int *b = s->env_box[k];
-        if (b[2] <= 0) continue;
-        e = launch_mask(mask, s->g, s->d_params, state, s->nbodies, b[0], b[1], b[2], b[3], st);
-        if (e != hipSuccess) return e;
+    PlaceArgs a{};
+    a.params = s->d_params;
+    a.nbodies = s->nbodies;
+    a.nsteps = n;
+    for (int i = 0; i < n; i++) {
+        a.mask[i] = masks[i];
+        a.state[i] = states[i];
     }
-    return hipSuccess;
+    a.t_base = s->t_dev;
+    a.t_off = t_off;
+    a.g = s->g;
+    int acc = 0;
+    for (int k = 0; k < kMaxBodies; k++) {
+        a.box_start[k] = acc;
+        const int *b = s->env_box[k];
+        const bool use = s->moving && k < s->nbodies && b[2] > 0 && b[3] > 0;
+        for (int q = 0; q < 4; q++) a.box[k][q] = use ? b[q] : 0;
+        acc += use ? b[2] * b[3] : 0;
+    }
+    a.box_start[kMaxBodies] = acc;
+    return launch_place(a, st);
 }
 
 hipError_t place_bodies(vplbm_sim s, int t_off, hipStream_t st)
 {
-    return place_bodies(s, t_off, st, s->mask, s->d_state);
+    uint8_t *m[1] = {s->mask};
+    BodyState *b[1] = {s->d_state};
+    return place_bodies_n(s, t_off, 1, st, m, b);
 }
 
 // Convective outlet: the previous-step outlet values start as the current state's last column.
@@ -220,7 +237,8 @@ bool two_step_ok(vplbm_sim s)
 hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st, int *flip)
 {
     const bool two = two_step_ok(s);
-    int src = first_src, j = 0;
+    int src = first_src;
+    int j = 0;
     while (j < n) {
         hipError_t e;
         if (two && n - j >= 2) {
@@ -228,8 +246,9 @@ hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st, int 
             if (s->moving) {
                 // the first step on the other mask, the second on the simulation's own: after
                 // the launch it holds the last step's bodies, as after one step per launch
-                e = place_bodies(s, j, st, s->mask_alt, s->d_state_alt);
-                if (e == hipSuccess) e = place_bodies(s, j + 1, st);
+                uint8_t *m[2] = {s->mask_alt, s->mask};
+                BodyState *b[2] = {s->d_state_alt, s->d_state};
+                e = place_bodies_n(s, j, 2, st, m, b);
                 if (e != hipSuccess) return e;
                 a.mask = s->mask_alt;
                 a.bodies = s->d_state_alt;
@@ -563,19 +582,20 @@ int vplbm_step(vplbm_sim s, int64_t nsteps)
     if (!valid(s)) return fail(VPLBM_EINVAL, "invalid handle");
     if (nsteps < 0) return fail(VPLBM_EINVAL, "nsteps must be >= 0");
     if (s->unstable) return fail(VPLBM_EUNSTABLE, "the simulation became unstable (non-finite or non-positive density)");
-    while (s->graph_k > 0 && nsteps >= s->graph_k) {
-        int rc = ensure_graph(s, s->cur);
-        if (rc) return rc;
-        HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
-        s->steps += s->graph_k;
-        nsteps -= s->graph_k;
-        s->cur ^= s->graph_flip[s->cur];
-    }
-    if (nsteps > 0) {
-        int flip = 0;
-        HIP_TRY(enqueue_steps(s, s->cur, (int)nsteps, s->stream, &flip));
-        s->steps += nsteps;
-        s->cur ^= flip;
+    while (nsteps > 0) {
+        const StepChunk c = next_chunk(nsteps, s->graph_k);
+        if (c.graph) {
+            int rc = ensure_graph(s, s->cur);
+            if (rc) return rc;
+            HIP_TRY(hipGraphLaunch(s->graph[s->cur], s->stream));
+            s->cur ^= s->graph_flip[s->cur];
+        } else {
+            int flip = 0;
+            HIP_TRY(enqueue_steps(s, s->cur, c.n, s->stream, &flip));
+            s->cur ^= flip;
+        }
+        s->steps += c.n;
+        nsteps -= c.n;
     }
     return VPLBM_OK;
 }

@@ -44,3 +44,18 @@ def test_profile_entries_follow_the_kernel_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("w", "f32", 1) is None      # taken on other sources
     assert bench.measured_traffic("w", "f16s", 2) is None     # not measured
     assert bench.profile_entry("valu", "w", "f32", 2) is None  # no such summary
+
+
+def test_cpu_baseline_reports_one_and_all_threads():
+    """The oracle leg of the benchmark times one thread and every thread it may use, on each
+    sample, and names the host CPU."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1812_05401_amd import inputs as I
+    c = I.cylinder_wake(64, 32, d=8.0, x0=16.0, re=100.0)
+    r = bench.cpu_baseline(c, [(c, 2, 4)])
+    assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["value"] > 0
+    assert r["threads_1"]["threads"] == 1 and r["threads_1"]["steps"] == 2
+    assert r["threads_all"]["threads"] == bench.host_threads() == r["cores"]
+    assert r["cpu_model"] and r["nproc"] >= 1
+    assert len(r["legs"]) == 2

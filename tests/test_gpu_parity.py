@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_1812_05401_amd import inputs as I
-from tests.helpers import force_scale, gpu_sim, oracle_sim, rel_err
+from tests.helpers import couette_l2, force_scale, gpu_sim, host_threads, oracle_sim, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -200,6 +200,44 @@ def test_full_size_cylinder_2048x512(gpu):
     g64 = gpu_sim(case, storage="f64")
     g64.step(130)
     assert max(compare(o, g64, TOL64, "cylinder_2048x512_f64")) <= TOL64
+
+
+def test_full_size_cylinder_2048x512_fp64_1000_steps(gpu):
+    """The 2048 x 512 cylinder wake at its full size, FP64 storage, after 1000 steps from the
+    uniform start (seven 128-step graph replays of two-step launches, then direct launches), in
+    the launch configuration the benchmark times for this lattice: populations, fields, mass and
+    force to 1e-12 relative of the oracle (run on the host's threads; its results do not depend
+    on their number)."""
+    case = I.cylinder_wake_2048x512()
+    o = oracle_sim(case, threads=host_threads())
+    o.step(1000)
+    g = gpu_sim(case, storage="f64")
+    assert g.steps_per_launch == 2
+    g.step(1000)
+    assert max(compare(o, g, TOL64, "cylinder_2048x512_f64_1000")) <= TOL64
+
+
+def test_taylor_couette_128_eq21_on_the_gpu(gpu):
+    """The 128 x 128 Taylor-Couette case over its whole 5000 steps on the GPU (FP64): the relative
+    L2 error of the velocity against the analytic profile (Eq. 21 through Eq. 20) is the oracle's
+    to 1e-9 of itself, about 2.7% (the staircase walls), and the fields match to 1e-12."""
+    case = I.taylor_couette_128()
+    o = oracle_sim(case, threads=host_threads())
+    o.step(case.steps)
+    g = gpu_sim(case)
+    g.step(case.steps)
+    assert max(compare(o, g, TOL64, "taylor_couette_128_5000")) <= TOL64
+    R1, R2 = case.bodies[0]["r"], case.bodies[1]["r"]
+    ud = case.bodies[0]["omega"] * R1
+    _, ux_o, uy_o = o.fields()
+    _, ux_g, uy_g = g.fields()
+    e_o = couette_l2(ux_o, uy_o, o.mask(), case.nx, R1, R2, ud)
+    e_g = couette_l2(ux_g, uy_g, g.mask(), case.nx, R1, R2, ud)
+    print(f"taylor_couette_128: L2 vs Eq. 21 GPU {e_g[0]:.6e} (v {e_g[1]:.6e}), "
+          f"oracle {e_o[0]:.6e} (v {e_o[1]:.6e})", flush=True)
+    assert 0.02 < e_g[0] < 0.03
+    for a, b in zip(e_g, e_o):
+        assert abs(a - b) <= 1e-9 * b
 
 
 def test_full_size_paper_cylinder_re500(gpu):

@@ -16,7 +16,7 @@ import pytest
 
 import oracle as O
 from paper_1812_05401_amd import inputs as I
-from tests.helpers import oracle_sim
+from tests.helpers import couette_l2, oracle_sim
 
 
 def _l2(u, ua, where):
@@ -133,17 +133,8 @@ def _couette(case_or_geom, coll=None, tau=None, lam=0.0, eta=1e-7, steps=None):
         s.init_uniform(1.0, 0.0, 0.0)
     s.step(steps)
     rho, ux, uy = s.fields()
-    ids = s.mask()
-    c = (L - 1) / 2
-    y, x = np.mgrid[0:L, 0:L]
-    dx, dy = x - c, y - c
-    r = np.hypot(dx, dy)
-    ut = -ud * R1 * r / (R2 ** 2 - R1 ** 2) + ud * R1 * R2 ** 2 / ((R2 ** 2 - R1 ** 2) * r)  # Eq. 21
-    ax, ay = -ut * dy / r, ut * dx / r
-    fluid = ids == 0
-    err_vec = math.sqrt(np.sum(((ux - ax) ** 2 + (uy - ay) ** 2)[fluid])
-                        / np.sum((ax ** 2 + ay ** 2)[fluid]))
-    return err_vec, _l2(uy, ay, fluid), s
+    err_vec, err_v = couette_l2(ux, uy, s.mask(), L, R1, R2, ud)   # Eqs. 20-21
+    return err_vec, err_v, s
 
 
 @pytest.mark.slow

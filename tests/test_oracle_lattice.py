@@ -314,3 +314,63 @@ def test_momentum_exchange_balances_the_body_momentum(collision):
         sc = o["fabs_sum"][k] + 1e-12
         assert abs(fx[k] - (p1[k][0] - p0[k][0] + o["fx"][k])) < 1e-12 * sc + 1e-15
         assert abs(fy[k] - (p1[k][1] - p0[k][1] + o["fy"][k])) < 1e-12 * sc + 1e-15
+
+
+def _vortex_channel(outlet, U=0.05, nx=200, ny=81, x0=140.0, y0=40.0, rc=6.0, vmax=0.005):
+    """A Gaussian vortex (swirl peak vmax at radius rc) carried by a uniform stream U toward the
+    outlet of a channel periodic in y."""
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    dx, dy = X - x0, Y - y0
+    amp = vmax / rc * np.exp(0.5 * (1.0 - (dx * dx + dy * dy) / rc ** 2))
+    s = O.OracleSim(nx, ny, O.SRT, tau=0.55, bc=(O.VELOCITY, outlet, O.PERIODIC, O.PERIODIC),
+                    u_in=(U, 0.0), threads=0)
+    s.init_fields(np.ones((ny, nx)), U - amp * dy, amp * dx)
+    return s, X
+
+
+def test_convective_outlet_lets_a_vortex_out_without_a_reflected_pressure_wave():
+    """Reading R13 pinned by what a convective outlet is for (Section 3.3: the wake's vortices must
+    leave the domain).  A vortex carried by the stream moves at the stream speed U, and while it
+    crosses the convective outlet the density disturbance stays at the level of the vortex's own
+    pressure deficit.  The zero-gradient outlet, at the same crossing, reflects a pressure wave
+    several times larger."""
+    U = 0.05
+    peak = {}
+    for name, outlet in (("convective", O.CONVECTIVE), ("zero_gradient", O.OUTFLOW)):
+        s, X = _vortex_channel(outlet, U)
+        cx, dmax = [], 0.0
+        for k in range(15):
+            s.step(100)
+            rho, ux, uy = s.fields()
+            e = (ux - U) ** 2 + uy ** 2
+            cx.append(float((e * X).sum() / e.sum()))
+            if s.steps_done >= 800:                    # the vortex reaches the outlet
+                dmax = max(dmax, float(np.abs(rho - 1.0).max()))
+        # the vortex (energy centroid) moves at U before it reaches the outlet: steps 200-800
+        assert abs((cx[7] - cx[1]) / 600.0 - U) < 0.05 * U, name
+        peak[name] = dmax
+    assert peak["convective"] < 3e-5
+    assert peak["zero_gradient"] > 4.0 * peak["convective"]
+
+
+def test_thread_count_gives_bitwise_the_same_run():
+    """The node loops may run on several threads; the per-step sums are added by one thread in
+    row-major order, so populations, observables and fields do not depend on the thread count
+    (moving bodies, whose mask is rebuilt every step, and the convective outlet included)."""
+    case = I.Case("threads", 61, 23, collision=I.MRT, tau=0.6, eta=1e-7,
+                  bc=I.CHANNEL_CONVECTIVE, u_in=(0.04, 0.0), u0=(0.04, 0.0),
+                  bodies=I.random_bodies(61, 23, 7, 2, moving=True, rmin=2, rmax=5))
+    runs = []
+    for th in (1, 3, 0):
+        s = O.OracleSim(case.nx, case.ny, O.MRT, tau=case.tau, eta=case.eta,
+                        bc=(O.VELOCITY, O.CONVECTIVE, O.FREESLIP, O.FREESLIP), u_in=case.u_in,
+                        threads=th)
+        s.set_bodies([orc_body(b) for b in case.bodies])
+        s.init_uniform(1.0, *case.u0)
+        s.step(37)
+        o = s.obs()
+        runs.append((s.populations(), o["mass"], o["fx"], o["fy"], *s.fields(), s.threads))
+    assert runs[1][-1] == 3 and runs[2][-1] >= 1
+    for r in runs[1:]:
+        for a, b in zip(runs[0][:-1], r[:-1]):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
