@@ -73,26 +73,6 @@ __device__ __forceinline__ void add_partials(const StepArgs &a, long long t, con
     }
 }
 
-// Body forces of one row of nodes: only waves holding solid nodes do any work, one pass per
-// body id present in the wave; lane 0 adds the wave's sums into the wave's own LDS partials.
-template <bool DPP>
-__device__ __forceinline__ void wave_forces(double *wave_acc, double fx, double fy, int id)
-{
-    unsigned long long solid = __ballot(id != 0);
-    while (solid) {
-        const int lead = __ffsll((unsigned long long)solid) - 1;
-        const int k = __shfl(id, lead, 64);
-        const bool mine = id == k;
-        const double sx = wave_sum<DPP>(mine ? -fx : 0.0);
-        const double sy = wave_sum<DPP>(mine ? -fy : 0.0);
-        if ((threadIdx.x & 63) == 0) {
-            wave_acc[1 + 2 * (k - 1)] += sx;
-            wave_acc[2 + 2 * (k - 1)] += sy;
-        }
-        solid &= ~__ballot(mine);
-    }
-}
-
 template <int S, bool NT>
 __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a)
 {
@@ -317,14 +297,25 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
 //   Segments: the host picks the number of segments per strip (a.nseg) so that the workgroups fill
 // the resident slots of the chip once (or a whole number of times); the segment of workgroup w is
 // rows [ny seg / nseg, ny (seg + 1) / nseg).
-template <int S, int TW, int R, bool NT, bool CONV, int V>
-__global__ __launch_bounds__(TW * R + 64) __attribute__((amdgpu_waves_per_eu((V == 1 || S == kF64 || S == kF32D) ? 1 : 7))) void step2s_kernel(StepArgs a)
+// V (timing variants): 0 halo wave, prefetch, 7 waves/SIMD; 1 halo wave, prefetch, no occupancy
+// target; 2 halo wave, no prefetch; 3 no halo wave (wave 0 computes the halo nodes after its own),
+// prefetch, 6 waves/SIMD; 4 as 3 without prefetch.
+template <int S, int V> constexpr bool strip_halo_wave() { return V <= 2; }
+template <int S, int TW, int R, int V> constexpr int strip_threads() { return TW * R + (strip_halo_wave<S, V>() ? 64 : 0); }
+template <int S, int V> constexpr int strip_waves_per_eu()
 {
-    constexpr bool PF = V != 2;                     // load step t's inputs one iteration ahead
+    return (S == kF64 || S == kF32D || V == 1) ? 1 : (strip_halo_wave<S, V>() ? 7 : 6);
+}
+
+template <int S, int TW, int R, bool NT, bool CONV, int V>
+__global__ __launch_bounds__((strip_threads<S, TW, R, V>())) __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<S, V>()))) void step2s_kernel(StepArgs a)
+{
+    constexpr bool PF = V != 2 && V != 4;           // load step t's inputs one iteration ahead
+    constexpr bool HW = strip_halo_wave<S, V>();    // a wave of its own for the halo columns
     using C = Codec<S>;
     using T = typename C::real;
     using E = typename C::elem;
-    constexpr int NTH = TW * R + 64;
+    constexpr int NTH = strip_threads<S, TW, R, V>();
     constexpr int NW = NTH / 64;
     constexpr int EW = TW + 2;                      // ring row: columns x0 - 1 .. x0 + TW
     constexpr int NR = 2 * R + 2;
@@ -378,6 +369,19 @@ __global__ __launch_bounds__(TW * R + 64) __attribute__((amdgpu_waves_per_eu((V 
         else col_live = false;
     }
     const bool col_own = strip_thread && ux < g.nx; // a column of this strip (not the halo)
+    // Without a halo wave, lanes 0 .. 2R - 1 of wave 0 also take the halo nodes of each row block.
+    int hlx = 0, hr = 0, hx1 = 0;
+    bool hcol_live = false;
+    if (!HW) {
+        hlx = lane < R ? -1 : TW;
+        hr = lane < R ? lane : lane - R;
+        hcol_live = (wave == 0) & (lane < 2 * R);
+        hx1 = x0 + hlx;
+        if (hx1 < 0 || hx1 >= g.nx) {
+            if (g.xper && hx1 >= -1 && hx1 <= g.nx) hx1 += hx1 < 0 ? g.nx : -g.nx;
+            else hcol_live = false;
+        }
+    }
     const int x2 = ux;                              // step t + 1 column (strip threads)
     // The strip, its halo and every pull of both steps stay clear of the x edges.
     const bool xin = (x0 >= 2) & (x0 + TW + 2 <= g.nx);
@@ -439,6 +443,27 @@ __global__ __launch_bounds__(TW * R + 64) __attribute__((amdgpu_waves_per_eu((V 
                 }
             }
             if (a.reduce) wave_forces<DPP>(wave_acc[0][wave], fx_d, fy_d, id);
+        }
+        if (!HW && wave == 0) {
+            // the halo nodes of this row block (never a column of this strip: no sums, no outlet)
+            const int uy = a1 + hr;
+            int y = uy;
+            bool live = hcol_live & (uy <= y1);
+            if (y < 0 || y >= g.ny) {
+                if (g.yper && y >= -1 && y <= g.ny) y += y < 0 ? g.ny : -g.ny;
+                else live = false;
+            }
+            if (live) {
+                int slot = base + hr;
+                if (slot >= NR) slot -= NR;
+                const int hid = *at(a.mask, unsigned(y * g.pitch + hx1));
+                T f[9];
+                const bool yin = (a1 >= 1) & (a1 + R <= g.ny - 1);
+                if (xin & yin) pull_interior<S>(src, hx1, y, g, f);
+                else pull<S>(src, hx1, y, g, out1, f);
+                relax_node_id(f, hid, a.bodies, g, a.p, hx1, y);
+                store_node<S>(ring, EN, unsigned(slot * EW + hlx + 1), f, unsigned(y * g.pitch + hx1), (unsigned)t);
+            }
         }
         __syncthreads();                            // rows a1 .. a1 + R - 1 of step t are in the ring
         if (PF && it + 1 < niter) prefetch(it + 1);
@@ -631,7 +656,7 @@ static int resident_slots(K kernel, int threads)
 template <int S, int TW, int R, bool NT, bool CONV, int V>
 static void launch2s_one(StepArgs a, hipStream_t st)
 {
-    constexpr int nth = TW * R + 64;
+    constexpr int nth = strip_threads<S, TW, R, V>();
     const int slots = resident_slots(step2s_kernel<S, TW, R, NT, CONV, V>, nth);
     a.nseg = strip_segments(a.g.nx, a.g.ny, TW, slots, 2 * R);
     const dim3 grid(((a.g.nx + TW - 1) / TW) * a.nseg), block(nth);
@@ -644,10 +669,16 @@ static void launch2s(const StepArgs &a, hipStream_t st)
     if (a.outlet.prev) {
         if (a.nt_store) launch2s_one<S, TW, R, true, true, 0>(a, st);
         else launch2s_one<S, TW, R, false, true, 0>(a, st);
-    } else if (S == kF32 && a.nt_store && a.strip == 2) {
+    } else if (a.nt_store && a.strip == 2) {
         launch2s_one<S, TW, R, true, false, 1>(a, st);
-    } else if (S == kF32 && a.nt_store && a.strip == 3) {
+    } else if (a.nt_store && a.strip == 3) {
         launch2s_one<S, TW, R, true, false, 2>(a, st);
+    } else if (a.strip == 4) {
+        if (a.nt_store) launch2s_one<S, TW, R, true, false, 3>(a, st);
+        else launch2s_one<S, TW, R, false, false, 3>(a, st);
+    } else if (a.strip == 5) {
+        if (a.nt_store) launch2s_one<S, TW, R, true, false, 4>(a, st);
+        else launch2s_one<S, TW, R, false, false, 4>(a, st);
     } else {
         if (a.nt_store) launch2s_one<S, TW, R, true, false, 0>(a, st);
         else launch2s_one<S, TW, R, false, false, 0>(a, st);

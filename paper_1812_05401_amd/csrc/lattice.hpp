@@ -694,6 +694,26 @@ __device__ __forceinline__ double wave_sum(double v)
 // The wave sum a kernel computing in T uses.
 template <typename T> constexpr bool wave_sum_dpp() { return sizeof(T) == 4; }
 
+// Body forces of one row of nodes: only waves holding solid nodes do any work, one pass per
+// body id present in the wave; lane 0 adds the wave's sums into the wave's own LDS partials.
+template <bool DPP>
+__device__ __forceinline__ void wave_forces(double *wave_acc, double fx, double fy, int id)
+{
+    unsigned long long solid = __ballot(id != 0);
+    while (solid) {
+        const int lead = __ffsll((unsigned long long)solid) - 1;
+        const int k = __shfl(id, lead, 64);
+        const bool mine = id == k;
+        const double sx = wave_sum<DPP>(mine ? -fx : 0.0);
+        const double sy = wave_sum<DPP>(mine ? -fy : 0.0);
+        if ((threadIdx.x & 63) == 0) {
+            wave_acc[1 + 2 * (k - 1)] += sx;
+            wave_acc[2 + 2 * (k - 1)] += sy;
+        }
+        solid &= ~__ballot(mine);
+    }
+}
+
 // Map a hardware workgroup id to a logical tile so that each XCD (workgroups are dealt to the 8
 // XCDs round-robin) works on one contiguous range of tiles, keeping x-neighbouring tiles, which
 // share cache lines through the x-shifted pulls, in the same L2.
