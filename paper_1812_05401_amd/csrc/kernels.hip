@@ -277,284 +277,6 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     }
 }
 
-// ---- two steps per launch, strip sweep ---------------------------------------------------------
-// Steps t and t + 1 of a strip of TW columns over a segment of rows [y0, y1) in one launch.  The
-// workgroup sweeps its segment upward, R rows per iteration.  Iteration i computes step t on R
-// rows of the strip and of its one-column halo on either side, from the planes in global memory,
-// into a ring of NR rows in LDS (rounded exactly as a global store would round it); after one
-// barrier it computes step t + 1 on the R rows one below, pulling from the ring, and stores them.
-// While it does, the loads of the next iteration's step-t rows are already in flight.  So each
-// workgroup keeps loads and stores going at once, and only the two halo columns and two rows per
-// segment are computed twice (against a one-node halo around every tile of the tile kernel).
-// Each node's arithmetic is the one-step kernel's, so the populations are bitwise those of two
-// one-step launches.
-//   Threads: TW x R for the strip's nodes (row r = thread / TW, whole waves per row), plus one
-// wave whose first 2R lanes take the halo columns x0 - 1 and x0 + TW of step t.
-//   Ring: level-t row uy is held in slot (uy - y0 + 1) mod NR.  Iteration i writes rows
-// y0 - 1 + iR + [0, R) and its second phase reads rows y0 - 3 + iR + [0, R + 2); with NR = 2R + 2
-// the rows the next iteration writes never share a slot with rows this iteration still reads, and
-// the barrier of the next iteration orders everything older.
-//   Segments: the host picks the number of segments per strip (a.nseg) so that the workgroups fill
-// the resident slots of the chip once (or a whole number of times); the segment of workgroup w is
-// rows [ny seg / nseg, ny (seg + 1) / nseg).
-// V (timing variants): 0 halo wave, prefetch, 7 waves/SIMD; 1 halo wave, prefetch, no occupancy
-// target; 2 halo wave, no prefetch; 3 no halo wave (wave 0 computes the halo nodes after its own),
-// prefetch, 6 waves/SIMD; 4 as 3 without prefetch.
-template <int S, int V> constexpr bool strip_halo_wave() { return V <= 2; }
-template <int S, int TW, int R, int V> constexpr int strip_threads() { return TW * R + (strip_halo_wave<S, V>() ? 64 : 0); }
-template <int S, int V> constexpr int strip_waves_per_eu()
-{
-    return (S == kF64 || S == kF32D || V == 1) ? 1 : (strip_halo_wave<S, V>() ? 7 : 6);
-}
-
-template <int S, int TW, int R, bool NT, bool CONV, int V>
-__global__ __launch_bounds__((strip_threads<S, TW, R, V>())) __attribute__((amdgpu_waves_per_eu(strip_waves_per_eu<S, V>()))) void step2s_kernel(StepArgs a)
-{
-    constexpr bool PF = V != 2 && V != 4;           // load step t's inputs one iteration ahead
-    constexpr bool HW = strip_halo_wave<S, V>();    // a wave of its own for the halo columns
-    using C = Codec<S>;
-    using T = typename C::real;
-    using E = typename C::elem;
-    constexpr int NTH = strip_threads<S, TW, R, V>();
-    constexpr int NW = NTH / 64;
-    constexpr int EW = TW + 2;                      // ring row: columns x0 - 1 .. x0 + TW
-    constexpr int NR = 2 * R + 2;
-    constexpr int EN = EW * NR;                     // elements per population plane of the ring
-    constexpr bool DPP = wave_sum_dpp<T>();
-    constexpr int odirs[3] = {3, 6, 7};             // the directions entering from x = nx
-    constexpr int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    constexpr int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    constexpr int mirror_y[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
-    static_assert(TW % 64 == 0 && R >= 2, "whole waves per row; two rows or more per iteration");
-    __shared__ E ring[9 * EN];
-    __shared__ double wave_acc[2][NW][kRingWidth];  // per-wave partials of steps t and t + 1
-    __shared__ T outl[3][NR];                       // convective outlet: step t's recorded values
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long long t = *a.t_base + a.t_off;
-    const Geom &g = a.g;
-    if (a.reduce) {
-        if (lane < kRingWidth) {
-            wave_acc[0][wave][lane] = 0.0;
-            wave_acc[1][wave][lane] = 0.0;
-        }
-        reduction_prologue(a, t, 2);
-    }
-    const int nstrips = (g.nx + TW - 1) / TW;
-    const int w = xcd_tile(blockIdx.x, gridDim.x);
-    const int strip = w % nstrips, seg = w / nstrips;
-    const int x0 = strip * TW;
-    const int y0 = int((long long)g.ny * seg / a.nseg), y1 = int((long long)g.ny * (seg + 1) / a.nseg);
-    const E *__restrict__ src = static_cast<const E *>(a.src);
-    E *__restrict__ dst = static_cast<E *>(a.dst);
-    const Outlet out1{a.outlet.prev, nullptr, a.outlet.u};   // step t reads the outlet, records nothing
-
-    // This thread's column (lx: -1 and TW are the halo) and row within an iteration.
-    const bool strip_thread = threadIdx.x < TW * R;
-    int lx, r;
-    bool col_live;
-    if (strip_thread) {
-        lx = threadIdx.x % TW;
-        r = __builtin_amdgcn_readfirstlane(threadIdx.x / TW);   // whole waves per row
-        col_live = true;
-    } else {
-        const int l = threadIdx.x - TW * R;
-        lx = l < R ? -1 : TW;
-        r = l < R ? l : l - R;
-        col_live = l < 2 * R;
-    }
-    const int ux = x0 + lx;                         // unwrapped column of step t
-    int x1 = ux;                                    // its lattice column
-    if (x1 < 0 || x1 >= g.nx) {
-        if (g.xper && x1 >= -1 && x1 <= g.nx) x1 += x1 < 0 ? g.nx : -g.nx;
-        else col_live = false;
-    }
-    const bool col_own = strip_thread && ux < g.nx; // a column of this strip (not the halo)
-    // Without a halo wave, lanes 0 .. 2R - 1 of wave 0 also take the halo nodes of each row block.
-    int hlx = 0, hr = 0, hx1 = 0;
-    bool hcol_live = false;
-    if (!HW) {
-        hlx = lane < R ? -1 : TW;
-        hr = lane < R ? lane : lane - R;
-        hcol_live = (wave == 0) & (lane < 2 * R);
-        hx1 = x0 + hlx;
-        if (hx1 < 0 || hx1 >= g.nx) {
-            if (g.xper && hx1 >= -1 && hx1 <= g.nx) hx1 += hx1 < 0 ? g.nx : -g.nx;
-            else hcol_live = false;
-        }
-    }
-    const int x2 = ux;                              // step t + 1 column (strip threads)
-    // The strip, its halo and every pull of both steps stay clear of the x edges.
-    const bool xin = (x0 >= 2) & (x0 + TW + 2 <= g.nx);
-    const int niter = (y1 - y0 + 1) / R + 1;
-
-    bool bad = false;
-    double mass1 = 0.0, mass2 = 0.0;
-    // Step t's inputs of the coming iteration, loaded one iteration ahead.
-    T pf[9];
-    int pid = 0;
-    bool plive = false;
-    auto prefetch = [&](int it) {
-        const int uy = y0 - 1 + it * R + r;
-        int y = uy;
-        bool live = col_live & (uy <= y1);
-        if (y < 0 || y >= g.ny) {
-            if (g.yper && y >= -1 && y <= g.ny) y += y < 0 ? g.ny : -g.ny;
-            else live = false;
-        }
-        plive = live;
-        if (live) {
-            pid = *at(a.mask, unsigned(y * g.pitch + x1));
-            const int a1 = y0 - 1 + it * R;
-            const bool yin = (a1 >= 1) & (a1 + R <= g.ny - 1);
-            if (xin & yin) pull_interior<S>(src, x1, y, g, pf);
-            else pull<S>(src, x1, y, g, out1, pf);
-        }
-    };
-    if (PF) prefetch(0);
-    int base = 0;                                   // (it * R) mod NR
-    for (int it = 0; it < niter; it++) {
-        const int a1 = y0 - 1 + it * R;             // first step-t row of this iteration
-        if (!PF) prefetch(it);
-        // ---- step t on row a1 + r
-        {
-            const int uy = a1 + r;
-            int y = uy;
-            if (y < 0 || y >= g.ny) y += y < 0 ? g.ny : -g.ny;   // live rows outside are periodic
-            int slot = base + r;
-            if (slot >= NR) slot -= NR;
-            double fx_d = 0.0, fy_d = 0.0;
-            int id = 0;
-            if (plive) {
-                T f[9];
-#pragma unroll
-                for (int k = 0; k < 9; k++) f[k] = pf[k];
-                const bool own = col_own & (uy >= y0) & (uy < y1);
-                if (CONV && x1 == g.nx - 1 && col_own)
-                    for (int k = 0; k < 3; k++) outl[k][slot] = f[odirs[k]];
-                const Macro<T> m = relax_node_id(f, pid, a.bodies, g, a.p, x1, y);
-                store_node<S>(ring, EN, unsigned(slot * EW + lx + 1), f, unsigned(y * g.pitch + x1), (unsigned)t);
-                if (own) {
-                    const double rho_d = 1.0 + double(m.drho);
-                    mass1 += rho_d;
-                    fx_d = double(m.fx);
-                    fy_d = double(m.fy);
-                    bad |= !(rho_d > 0.0 && rho_d < 1e30);
-                    id = pid;
-                }
-            }
-            if (a.reduce) wave_forces<DPP>(wave_acc[0][wave], fx_d, fy_d, id);
-        }
-        if (!HW && wave == 0) {
-            // the halo nodes of this row block (never a column of this strip: no sums, no outlet)
-            const int uy = a1 + hr;
-            int y = uy;
-            bool live = hcol_live & (uy <= y1);
-            if (y < 0 || y >= g.ny) {
-                if (g.yper && y >= -1 && y <= g.ny) y += y < 0 ? g.ny : -g.ny;
-                else live = false;
-            }
-            if (live) {
-                int slot = base + hr;
-                if (slot >= NR) slot -= NR;
-                const int hid = *at(a.mask, unsigned(y * g.pitch + hx1));
-                T f[9];
-                const bool yin = (a1 >= 1) & (a1 + R <= g.ny - 1);
-                if (xin & yin) pull_interior<S>(src, hx1, y, g, f);
-                else pull<S>(src, hx1, y, g, out1, f);
-                relax_node_id(f, hid, a.bodies, g, a.p, hx1, y);
-                store_node<S>(ring, EN, unsigned(slot * EW + hlx + 1), f, unsigned(y * g.pitch + hx1), (unsigned)t);
-            }
-        }
-        __syncthreads();                            // rows a1 .. a1 + R - 1 of step t are in the ring
-        if (PF && it + 1 < niter) prefetch(it + 1);
-        // ---- step t + 1 on row a1 - 1 + r (strip threads)
-        if (strip_thread) {
-            const int y = a1 - 1 + r;
-            double fx_d = 0.0, fy_d = 0.0;
-            int id = 0;
-            if ((y >= y0) & (y < y1) & (x2 < g.nx)) {
-                id = *at(a.mask2, unsigned(y * g.pitch + x2));
-                // ring slots of rows y - 1, y, y + 1 (ring offsets r - 2, r - 1, r)
-                int sc = base + r - 1;
-                sc += sc < 0 ? NR : 0;
-                sc -= sc >= NR ? NR : 0;
-                const int sm = sc == 0 ? NR - 1 : sc - 1;
-                const int sp = sc == NR - 1 ? 0 : sc + 1;
-                T f[9];
-                const bool shifts = (g.xper | ((x2 > 0) & (x2 < g.nx - 1))) & (g.yper | ((y > 0) & (y < g.ny - 1)));
-                if (shifts) {
-                    const unsigned ec = unsigned(sc * EW + lx + 1), em = unsigned(sm * EW + lx + 1),
-                                   ep = unsigned(sp * EW + lx + 1);
-                    f[0] = C::load(ring, ec, W<T>::rest);
-                    f[1] = C::load(ring + 1 * EN, ec - 1, W<T>::axis);
-                    f[2] = C::load(ring + 2 * EN, em, W<T>::axis);
-                    f[3] = C::load(ring + 3 * EN, ec + 1, W<T>::axis);
-                    f[4] = C::load(ring + 4 * EN, ep, W<T>::axis);
-                    f[5] = C::load(ring + 5 * EN, em - 1, W<T>::diag);
-                    f[6] = C::load(ring + 6 * EN, em + 1, W<T>::diag);
-                    f[7] = C::load(ring + 7 * EN, ep + 1, W<T>::diag);
-                    f[8] = C::load(ring + 8 * EN, ep - 1, W<T>::diag);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 9; k++) {
-                        // edge_source without the periodic wrap (the halo holds the wrapped nodes)
-                        int sx = x2 - cx[k], sy = y - cy[k], pa = k;
-                        if ((sy < 0 || sy >= g.ny) && !g.yper) { sy = y; pa = mirror_y[k]; }
-                        if ((sx < 0 || sx >= g.nx) && !g.xper) sx = sx < 0 ? 0 : g.nx - 1;
-                        const int ss = sy == y ? sc : (sy < y ? sm : sp);
-                        f[k] = C::load(ring + pa * EN, unsigned(ss * EW + (sx - x0 + 1)), weight<T>(k));
-                    }
-                }
-                if (CONV && x2 == g.nx - 1) {
-                    // the outlet rule with step t's values from the ring; the neighbour column's
-                    // sources of 3, 6, 7 are column nx - 1 (rows y, y - 1, y + 1, mirrored at a
-                    // free-slip edge)
-                    const T u = T(a.outlet.u);
-                    T *next = static_cast<T *>(a.outlet.next);
-                    for (int k = 0; k < 3; k++) {
-                        const int d = odirs[k];
-                        int sy = y - cy[d], pa = d;
-                        if ((sy < 0 || sy >= g.ny) && !g.yper) { sy = y; pa = mirror_y[d]; }
-                        const int ss = sy == y ? sc : (sy < y ? sm : sp);
-                        const T nb = C::load(ring + pa * EN, unsigned(ss * EW + (g.nx - 1 - x0 + 1)), weight<T>(d));
-                        f[d] = (outl[k][sc] + u * nb) / (T(1) + u);
-                    }
-                    for (int k = 0; k < 3; k++) next[k * g.ny + y] = f[odirs[k]];
-                }
-                const Macro<T> m = relax_node_id(f, id, a.bodies2, g, a.p, x2, y);
-                const unsigned i = y * g.pitch + x2;
-                store_node<S, NT>(dst, g.plane, i, f, i, (unsigned)(t + 1));
-                const double rho_d = 1.0 + double(m.drho);
-                mass2 += rho_d;
-                fx_d = double(m.fx);
-                fy_d = double(m.fy);
-                bad |= !(rho_d > 0.0 && rho_d < 1e30);
-            }
-            if (a.reduce) wave_forces<DPP>(wave_acc[1][wave], fx_d, fy_d, id);
-        }
-        base += R;
-        base -= base >= NR ? NR : 0;
-    }
-    if (a.reduce) {
-        const double m1 = wave_sum<DPP>(mass1), m2 = wave_sum<DPP>(mass2);
-        if (lane == 0) {
-            wave_acc[0][wave][0] += m1;
-            wave_acc[1][wave][0] += m2;
-        }
-        if (__ballot(bad) && lane == 0) atomicOr(a.status, 1u);
-        __syncthreads();
-        add_partials(a, t, &wave_acc[0][0][0], NW);
-        if (threadIdx.x >= 64 && threadIdx.x < 64 + kRingWidth) {
-            // the second step's rows by the second wave, as add_partials does for the first
-            const int q = threadIdx.x - 64;
-            double v = 0.0;
-            for (int k = 0; k < NW; k++) v += wave_acc[1][k][q];
-            double *slot = acc_set(a, t + 1) + (blockIdx.x & (kSub - 1)) * kRingWidth;
-            if (v != 0.0) unsafeAtomicAdd(slot + q, v);
-        }
-    }
-}
-
 __global__ void fold_kernel(StepArgs a)
 {
     const long long t = *a.t_base;
@@ -627,79 +349,8 @@ static void launch2(const StepArgs &a, hipStream_t st)
     }
 }
 
-int strip_segments(int nx, int ny, int tw, int slots, int min_rows)
-{
-    const int nstrips = (nx + tw - 1) / tw;
-    int nseg = (slots + nstrips / 2) / nstrips;       // nearest whole number of rounds
-    if (nseg < 1) nseg = 1;
-    const int cap = ny / (min_rows > 0 ? min_rows : 1);
-    if (nseg > cap) nseg = cap > 0 ? cap : 1;
-    return nseg;
-}
-
-// Resident workgroups of a kernel on the current device (all CUs), looked up once per device.
-template <typename K>
-static int resident_slots(K kernel, int threads)
-{
-    static int cache[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    if (!cache[dev]) {
-        int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
-        cache[dev] = per_cu * cus;
-    }
-    return cache[dev];
-}
-
-template <int S, int TW, int R, bool NT, bool CONV, int V>
-static void launch2s_one(StepArgs a, hipStream_t st)
-{
-    constexpr int nth = strip_threads<S, TW, R, V>();
-    const int slots = resident_slots(step2s_kernel<S, TW, R, NT, CONV, V>, nth);
-    a.nseg = strip_segments(a.g.nx, a.g.ny, TW, slots, 2 * R);
-    const dim3 grid(((a.g.nx + TW - 1) / TW) * a.nseg), block(nth);
-    step2s_kernel<S, TW, R, NT, CONV, V><<<grid, block, 0, st>>>(a);
-}
-
-template <int S, int TW, int R>
-static void launch2s(const StepArgs &a, hipStream_t st)
-{
-    if (a.outlet.prev) {
-        if (a.nt_store) launch2s_one<S, TW, R, true, true, 0>(a, st);
-        else launch2s_one<S, TW, R, false, true, 0>(a, st);
-    } else if (a.nt_store && a.strip == 2) {
-        launch2s_one<S, TW, R, true, false, 1>(a, st);
-    } else if (a.nt_store && a.strip == 3) {
-        launch2s_one<S, TW, R, true, false, 2>(a, st);
-    } else if (a.strip == 4) {
-        if (a.nt_store) launch2s_one<S, TW, R, true, false, 3>(a, st);
-        else launch2s_one<S, TW, R, false, false, 3>(a, st);
-    } else if (a.strip == 5) {
-        if (a.nt_store) launch2s_one<S, TW, R, true, false, 4>(a, st);
-        else launch2s_one<S, TW, R, false, false, 4>(a, st);
-    } else {
-        if (a.nt_store) launch2s_one<S, TW, R, true, false, 0>(a, st);
-        else launch2s_one<S, TW, R, false, false, 0>(a, st);
-    }
-}
-
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st)
 {
-    if (a.strip) {
-        switch (storage) {
-        case kF64: launch2s<kF64, 64, 4>(a, st); break;
-        case kF32D: launch2s<kF32D, 64, 4>(a, st); break;
-        case kF32: launch2s<kF32, 128, 4>(a, st); break;
-        case kF16S: launch2s<kF16S, 128, 4>(a, st); break;
-        case kBF16S: launch2s<kBF16S, 128, 4>(a, st); break;
-        case kF16SR: launch2s<kF16SR, 128, 4>(a, st); break;
-        case kBF16SR: launch2s<kBF16SR, 128, 4>(a, st); break;
-        default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
     // 2-byte storage: tall tiles once there are enough of them (4 M nodes and up)
     const bool tall = (long long)((a.g.nx + 127) / 128) * ((a.g.ny + 15) / 16) >= 2048;
 #define VPLBM_STEP2(S) (tall ? launch2<S, 128, 16>(a, st) : launch2<S, 128, 8>(a, st))

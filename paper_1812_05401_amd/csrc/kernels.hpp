@@ -46,8 +46,6 @@ struct StepArgs {
     int bx_log2, by;         // workgroup = (1 << bx_log2) x by threads
     int rows;                // each thread updates `rows` nodes, by rows apart
     int nt_store;            // 1: non-temporal population stores (buffers larger than the cache)
-    int strip;               // two-step launches: 1 = strip-sweep kernel, 0 = tile kernel
-    int nseg;                // strip-sweep kernel: row segments per strip (set by the launcher)
     NodeParams p;
 };
 
@@ -60,10 +58,6 @@ hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st);
 // Steps *t_base + t_off and the one after in one launch, from a.src into a.dst; the second step
 // takes its mask and body states from a.mask2 / a.bodies2 (no convective outlet).
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st);
-// The strip-sweep kernel's geometry for a lattice: strips of `tw` columns and `nseg` row segments
-// each, so that nstrips x nseg workgroups fill the `slots` resident workgroup slots of the chip
-// once (or a whole number of times), with segments of at least `min_rows` rows.
-int strip_segments(int nx, int ny, int tw, int slots, int min_rows);
 
 // Per-node density and penalized velocity of the current state into dense FP64 arrays.
 hipError_t launch_readback(int storage, const StepArgs &a, double *rho, double *ux, double *uy,

@@ -128,7 +128,6 @@ struct vplbm_sim_s {
     bool unstable = false;
     NodeParams params{};
     int nt_store = 0;
-    int strip = 0;                       // two-step launches by the strip-sweep kernel
     double *snap = nullptr;              // convergence residual: [2][ny*nx] velocity snapshot,
     double *rpart = nullptr;             // then per-workgroup partials and the two sums
     bool have_snap = false;
@@ -179,7 +178,6 @@ StepArgs step_args(vplbm_sim s, int src, int t_off)
     a.by = s->ts.by;
     a.rows = s->ts.rows;
     a.nt_store = s->nt_store;
-    a.strip = s->strip;
     a.p = s->params;
     return a;
 }
@@ -444,8 +442,6 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     s->nt_store = 2 * s->buf_bytes > ((size_t)192 << 20) ? 1 : 0;
     if (const char *e = getenv("VPLBM_NT_STORE")) s->nt_store = atoi(e) ? 1 : 0;
     if (const char *e = getenv("VPLBM_TWO_STEP")) s->two_step = atoi(e) != 0;   // 0: one step per launch
-    s->strip = 0;
-    if (const char *e = getenv("VPLBM_STRIP")) s->strip = atoi(e);               // 1: strip-sweep kernel
     struct { void **p; size_t n; } allocs[] = {
         {&s->buf[0], s->buf_bytes}, {&s->buf[1], s->buf_bytes},
         {(void **)&s->mask, (size_t)g.pitch * g.ny},

@@ -144,155 +144,3 @@ def test_pool_buffer_follows_the_launch_sequence():
                     assert pool_buf(done, spl) == buf
                 if stop_at is not None and done == stop_at and tgt > done + 1:
                     tgt = done + 1
-
-
-def strip_segments(nx, ny, tw, slots, min_rows):
-    """The launcher's segments per strip (kernels.hip strip_segments)."""
-    nstrips = -(-nx // tw)
-    nseg = max(1, (slots + nstrips // 2) // nstrips)
-    cap = ny // max(min_rows, 1)
-    if nseg > cap:
-        nseg = cap if cap > 0 else 1
-    return nseg
-
-
-def check_strip_lattice(nx, ny, xper, yper, tw, R, nseg, outlet=False):
-    """Model of step2s_kernel: every workgroup (strip, segment), every iteration, every thread.
-    Checks that each ring read of the second step names the node and plane the one-step rule
-    names, that it was written in this or the previous iteration and not overwritten since (a
-    slot written by the next iteration's first phase is never one this iteration's second phase
-    reads), that the inner fast paths only take interior nodes, and that every lattice node is
-    owned once in each step."""
-    nr = 2 * R + 2
-    ew = tw + 2
-    nstrips = -(-nx // tw)
-    own1, own2 = [], []
-    for w in range(nstrips * nseg):
-        strip, seg = w % nstrips, w // nstrips
-        x0 = strip * tw
-        y0, y1 = ny * seg // nseg, ny * (seg + 1) // nseg
-        niter = (y1 - y0 + 1) // R + 1
-        xin = x0 >= 2 and x0 + tw + 2 <= nx
-        threads = []                      # (lx, r, strip thread)
-        for tid in range(tw * R):
-            threads.append((tid % tw, tid // tw, True))
-        for l in range(2 * R):
-            threads.append((-1 if l < R else tw, l if l < R else l - R, False))
-        ring = {}                         # slot -> (ly, x, y) written by the first phase
-        age = {}                          # slot -> iteration that wrote it
-        outl = {}
-        for it in range(niter):
-            a1 = y0 - 1 + it * R
-            base = (it * R) % nr
-            written_now = set()
-            for lx, r, st in threads:
-                ux = x0 + lx
-                x1, live = ux, True
-                if x1 < 0 or x1 >= nx:
-                    if xper and -1 <= x1 <= nx:
-                        x1 += nx if x1 < 0 else -nx
-                    else:
-                        live = False
-                uy = a1 + r
-                y, live = uy, live and uy <= y1
-                if y < 0 or y >= ny:
-                    if yper and -1 <= y <= ny:
-                        y += ny if y < 0 else -ny
-                    else:
-                        live = False
-                if not live:
-                    continue
-                assert 0 <= x1 < nx and 0 <= y < ny
-                if xin and a1 >= 1 and a1 + R <= ny - 1:
-                    assert 0 < x1 < nx - 1 and 0 < y < ny - 1      # pull_interior
-                slot = base + r
-                slot -= nr if slot >= nr else 0
-                assert slot == (uy - y0 + 1) % nr
-                ring[(slot, lx + 1)] = (x1, y)
-                age[(slot, lx + 1)] = it
-                written_now.add(slot)
-                col_own = st and ux < nx
-                if col_own and y0 <= uy < y1:
-                    own1.append((x1, y))
-                if outlet and x1 == nx - 1 and col_own:
-                    outl[slot] = (x1, y)
-            # second phase (strip threads)
-            read_slots = set()
-            for lx, r, st in threads:
-                if not st:
-                    continue
-                x2, y = x0 + lx, a1 - 1 + r
-                if not (y0 <= y < y1 and x2 < nx):
-                    continue
-                own2.append((x2, y))
-                sc = base + r - 1
-                sc += nr if sc < 0 else 0
-                sc -= nr if sc >= nr else 0
-                sm = nr - 1 if sc == 0 else sc - 1
-                sp = 0 if sc == nr - 1 else sc + 1
-                assert sc == (y - y0 + 1) % nr
-                shifts = (xper or 0 < x2 < nx - 1) and (yper or 0 < y < ny - 1)
-                for a in range(9):
-                    if shifts:
-                        sx, sy, pa = x2 - CX[a], y - CY[a], a
-                    else:
-                        sx, sy, pa = x2 - CX[a], y - CY[a], a
-                        if (sy < 0 or sy >= ny) and not yper:
-                            sy, pa = y, MIRROR_Y[a]
-                        if (sx < 0 or sx >= nx) and not xper:
-                            sx = 0 if sx < 0 else nx - 1
-                    ss = sc if sy == y else (sm if sy < y else sp)
-                    col = sx - x0 + 1
-                    assert 0 <= col < ew and 0 <= ss < nr
-                    key = (ss, col)
-                    assert key in ring, (nx, ny, x2, y, a)
-                    assert age[key] in (it, it - 1)
-                    gx, gy, gpa = edge_source(a, x2, y, nx, ny, xper, yper)
-                    assert ring[key] == (gx, gy) and pa == gpa, (nx, ny, x2, y, a)
-                    read_slots.add(ss)
-                if outlet and x2 == nx - 1:
-                    assert outl[sc] == (x2, y)
-                    for d in (3, 6, 7):
-                        sy, pa = y - CY[d], d
-                        if (sy < 0 or sy >= ny) and not yper:
-                            sy, pa = y, MIRROR_Y[d]
-                        ss = sc if sy == y else (sm if sy < y else sp)
-                        gx, gy, gpa = edge_source(d, nx - 2, y, nx, ny, 0, yper)
-                        assert ring[(ss, nx - 1 - x0 + 1)] == (gx, gy) and pa == gpa
-            # the next iteration's first phase must not write a slot read here
-            nxt = {(((it + 1) * R + r) % nr) for r in range(R)}
-            assert not (nxt & read_slots)
-    everything = sorted((x, y) for x in range(nx) for y in range(ny))
-    assert sorted(own1) == everything
-    assert sorted(own2) == everything
-
-
-STRIP_SIZES = [(3, 3), (5, 4), (64, 8), (130, 17), (257, 31), (129, 3), (3, 40), (200, 45)]
-
-
-@pytest.mark.parametrize("tw,R", [(128, 4), (64, 4), (64, 8)])
-def test_strip_sweep_reads_what_the_first_step_wrote(tw, R):
-    for (nx, ny), xper, yper in itertools.product(STRIP_SIZES, (0, 1), (0, 1)):
-        for slots in (7, 768):
-            nseg = strip_segments(nx, ny, tw, slots, 2 * R)
-            check_strip_lattice(nx, ny, xper, yper, tw, R, nseg)
-        # segments of every height down to one row
-        for nseg in sorted({1, 2, min(ny, 5)}):
-            check_strip_lattice(nx, ny, xper, yper, tw, R, nseg)
-
-
-@pytest.mark.parametrize("tw,R", [(128, 4), (64, 4)])
-def test_strip_sweep_convective_outlet_lookups(tw, R):
-    for (nx, ny), yper in itertools.product([(3, 3), (5, 7), (129, 9), (150, 40), (257, 31)], (0, 1)):
-        for nseg in (1, 3):
-            check_strip_lattice(nx, ny, 0, yper, tw, R, min(nseg, ny), outlet=True)
-
-
-def test_strip_segments_fill_the_chip():
-    # 8192 x 2048 FP32: 64 strips of 128, 768 slots -> 12 segments of ~171 rows, one round
-    assert strip_segments(8192, 2048, 128, 768, 8) == 12
-    # the paper's 6048 x 2016 case: 48 strips -> 16 segments
-    assert strip_segments(6048, 2016, 128, 768, 8) == 16
-    # small lattices: segments of at least min_rows rows
-    assert strip_segments(100, 20, 128, 768, 8) == 2
-    assert strip_segments(100, 5, 128, 768, 8) == 1
