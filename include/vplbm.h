@@ -184,6 +184,17 @@ int vplbm_force_series(vplbm_sim s, int64_t first, int64_t count, double *out);
    in vplbm_obs (the body's own momentum changes average out).  Synchronizes. */
 int vplbm_momentum_exchange(vplbm_sim s, double *fx, double *fy);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc): vplbm_momentum_exchange without any allocation and
+   without synchronizing.  out: device memory of 2 * VPLBM_MAX_BODIES doubles, receiving (fx0, fy0,
+   fx1, fy1, ...) of the current state, written asynchronously on the simulation's stream (the
+   caller synchronizes before reading).  The sums run in a fixed order, so repeated calls give the
+   same value.  Partial sums go through a static device array of the library, one per GPU (65,536
+   rows of 17 doubles, 8.5 MiB, held until the process ends) and shared by every call on that
+   GPU: calls that overlap on one GPU (on different streams) race.  EINVAL: bad handle, out NULL
+   or not device memory, or a lattice of more than 16,777,216 nodes (the rows the array holds). */
+int vplbm_momentum_exchange_noalloc(vplbm_sim s, double *out);
+
 /* Number of steps done and the handle's stream (hipStream_t). */
 int vplbm_steps_done(vplbm_sim s, int64_t *steps);
 int vplbm_stream(vplbm_sim s, void **stream);

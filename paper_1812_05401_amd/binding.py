@@ -79,6 +79,7 @@ SIGNATURES = [
     ("vplbm_get_mask", C.c_int, [C.c_void_p, C.POINTER(C.c_uint8)]),
     ("vplbm_force_series", C.c_int, [C.c_void_p, C.c_int64, C.c_int64, _dp]),
     ("vplbm_momentum_exchange", C.c_int, [C.c_void_p, _dp, _dp]),
+    ("vplbm_momentum_exchange_noalloc", C.c_int, [C.c_void_p, C.c_void_p]),
     ("vplbm_residual", C.c_int, [C.c_void_p, _dp]),
     ("vplbm_steps_done", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("vplbm_steps_per_launch", C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
@@ -243,6 +244,12 @@ def vplbm_momentum_exchange(h, nbodies):
     fx, fy = np.zeros(MAX_BODIES), np.zeros(MAX_BODIES)
     check(load().vplbm_momentum_exchange(h, _ptr(fx), _ptr(fy)))
     return fx[:nbodies], fy[:nbodies]
+
+
+def vplbm_momentum_exchange_noalloc(h, out_ptr):
+    """Momentum exchange into device memory at out_ptr (2 * MAX_BODIES doubles), asynchronously
+    on the simulation's stream, without allocating (the library's static scratch)."""
+    check(load().vplbm_momentum_exchange_noalloc(h, C.c_void_p(int(out_ptr))))
 
 
 def vplbm_residual(h):

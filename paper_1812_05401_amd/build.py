@@ -13,8 +13,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvplbm.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "runtime.hip", "pool.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "lattice.hpp", "internal.hpp", "pool_policy.hpp", "step_plan.hpp")] + [
+SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "runtime.hip", "pool.hip", "static_scratch.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "lattice.hpp", "internal.hpp", "pool_policy.hpp", "step_plan.hpp", "static_scratch.hpp")] + [
     os.path.join(INCLUDE, "vplbm.h")]
 ARCH = os.environ.get("VPLBM_OFFLOAD_ARCH", "gfx950")
 

@@ -17,6 +17,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "static_scratch.hpp"
 #include "step_plan.hpp"
 #include "vplbm.h"
 
@@ -119,6 +120,7 @@ struct vplbm_sim_s {
     size_t staging_bytes = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = 0;                      // the device current at create (holds all the memory)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_flip[2] = {0, 0};          // 1: a replay moves the state to the other buffer
@@ -411,6 +413,12 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     if (rc) return rc;
     vplbm_sim s = new vplbm_sim_s();
     s->cfg = *cfg;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(VPLBM_EHIP, "no current device");
+    }
+    // the allocation-free entry point's scratch on this device (an error is reported by that call)
+    if (static_scratch_init() != VPLBM_OK) host_log("static scratch: %s", vplbm_last_error());
     s->storage = cfg->storage;
     s->ring_len = cfg->ring ? cfg->ring : 4096;
     s->graph_k = graph_chunk();
@@ -730,6 +738,20 @@ int vplbm_momentum_exchange(vplbm_sim s, double *fx, double *fy)
         fy[k] = out[2 * k + 1];
     }
     return VPLBM_OK;
+}
+
+int vplbm_momentum_exchange_noalloc(vplbm_sim s, double *out)
+{
+    if (!valid(s) || !out) return fail(VPLBM_EINVAL, "invalid handle or NULL output");
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, out) != hipSuccess ||
+        (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+        (void)hipGetLastError();
+        return fail(VPLBM_EINVAL, "out must be device memory");
+    }
+    double *sp = static_scratch(s->device);
+    if (!sp) return fail(VPLBM_EHIP, "the static scratch of device %d could not be located", s->device);
+    return launch_exchange_static(s->storage, step_args(s, s->cur, 0), sp, out, s->stream);
 }
 
 int vplbm_residual(vplbm_sim s, double *residual)
