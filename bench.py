@@ -319,7 +319,8 @@ def main():
                          "oscillating_cylinder_8192x2048) in the storage formats of --storages for "
                          "--steps steps and print the comparison against FP64")
     ap.add_argument("--dump", default="", help="with --precision-study: .npz for the series")
-    ap.add_argument("--sweep", default="", choices=["", "fig3", "fig12", "table1", "fig5", "fig14"],
+    ap.add_argument("--sweep", default="", choices=["", "fig3", "fig12", "fig12_readings", "table1",
+                                                    "fig5", "fig14"],
                     help="instead of the benchmark: run one of the paper's parameter sweeps "
                          "through the serving pool and print the L2 errors (fig5, fig14: steps "
                          "to convergence under the early stop)")
@@ -327,6 +328,8 @@ def main():
                     help="with --sweep: retire each point early once its convergence residual "
                          "over --stop-every steps is below this tolerance")
     ap.add_argument("--stop-every", type=int, default=1000)
+    ap.add_argument("--sweep-steps-scale", type=int, default=1,
+                    help="with --sweep fig12_readings: run each point this many times longer")
     ap.add_argument("--me-every", type=int, default=0,
                     help="with --precision-study: sample the momentum-exchange force every N steps")
     ap.add_argument("--storages", default="f64,f32,f32d,f16s,f16sr,bf16s,bf16sr",
@@ -334,6 +337,16 @@ def main():
     ap.add_argument("--stats-from", type=int, default=-1,
                     help="with --precision-study: first step of the statistics window (default: half)")
     ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--force-regions", default="", metavar="WORKLOAD",
+                    help="instead of the benchmark: split the drag of WORKLOAD (cylinder_wake_2048x512 "
+                         "or cylinder_wake_8192x2048) into the body's surface layer and interior, "
+                         "for the storages of --storages (time means from --stats-from on)")
+    ap.add_argument("--sensitivity", default="", choices=["", "re500"],
+                    help="instead of the benchmark: run the variants of the paper's Re = 500 "
+                         "cylinder (outlet rule, eta, inlet and outlet distance, collision, "
+                         "resolution, channel height) and print C_D, C_Lrms and St of each")
+    ap.add_argument("--variants", default="",
+                    help="with --sensitivity: comma-separated labels of the variants to run (all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: there is no multi-GPU path (asked for "
@@ -355,6 +368,7 @@ def main():
     if args.sweep:
         from paper_1812_05401_amd import sweeps
         pts = {"fig3": sweeps.fig3_shear, "fig12": sweeps.fig12_couette,
+               "fig12_readings": lambda: sweeps.fig12_readings(args.sweep_steps_scale),
                "table1": sweeps.table1_grids, "fig5": sweeps.fig5_convergence,
                "fig14": sweeps.fig14_convergence}[args.sweep]()
         stop = (args.stop, args.stop_every) if args.stop > 0 else sweeps.CONVERGENCE_STOP.get(args.sweep)
@@ -365,6 +379,26 @@ def main():
         print(json.dumps({"sweep": args.sweep, "points": len(pts), "stop": stop,
                           "lattice_updates": lups, "wall_s": wall, "mlups": lups / wall / 1e6,
                           "results": res}), flush=True)
+        return
+    if args.force_regions:
+        from paper_1812_05401_amd import study
+        mk = {"cylinder_wake_2048x512": I.cylinder_wake_2048x512,
+              "cylinder_wake_8192x2048": lambda: I.cylinder_wake_8192x2048("f32")}[args.force_regions]
+        res = study.force_region_study(mk(), storages=tuple(args.storages.split(",")),
+                                       steps=args.steps,
+                                       first=args.steps // 2 if args.stats_from < 0 else args.stats_from,
+                                       log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+        print(json.dumps(res), flush=True)
+        return
+    if args.sensitivity:
+        from paper_1812_05401_amd import study
+        cases = I.paper_cylinder_sensitivity(args.storage or "f32")
+        if args.variants:
+            keep = args.variants.split(",")
+            cases = [c for c in cases if c.name.replace("paper_cylinder_re500_", "") in keep]
+        res = study.sensitivity(cases, dump_dir=os.path.dirname(args.dump) if args.dump else None,
+                                log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+        print(json.dumps({"sensitivity": args.sensitivity, "runs": res}), flush=True)
         return
     if args.precision_study:
         from paper_1812_05401_amd import study

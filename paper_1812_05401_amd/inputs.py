@@ -114,6 +114,43 @@ def paper_cylinder_re500(storage="f32", steps=500_000) -> Case:
                 bodies=[body("disk", nx - 25 * d, ny / 2.0, r=d / 2.0)], steps=steps, diameter=d)
 
 
+def paper_cylinder_variant(label, storage="f32", upstream=5.0, downstream=25.0, height=10.0,
+                           scale=1.0, collision=SRT, eta=1e-7, outlet=CONVECTIVE) -> Case:
+    """The paper's Re = 500 cylinder (paper_cylinder_re500) with one setting changed, for a
+    sensitivity study: the inlet `upstream` diameters before the cylinder centre (5 in the paper;
+    the paper's lattice puts it 1023 nodes = 5.09 D from the inlet, kept for every variant), the
+    outlet `downstream` diameters after it (25), the channel `height` in diameters (10), the
+    resolution (`scale` times 201 nodes per diameter, Re and U kept, so tau follows Eq. 6), the
+    collision (SRT in the paper; MRT with Lambda = 3/16), eta, and the outlet rule (convective,
+    R13, or zero-gradient).  Steps and the statistics window scale with D / U."""
+    d = 201.0 * scale
+    re = 0.05 * 201.0 / ((0.56 - 0.5) / 3.0)          # 502.5, the paper's case
+    up = int(round(1023 * scale + (upstream - 5.0) * d))
+    nx = up + int(round(downstream * d))
+    ny = int(round(2016 * scale * height / 10.0))
+    bc = (VELOCITY, CONVECTIVE if outlet == CONVECTIVE else OUTFLOW, FREESLIP, FREESLIP)
+    return Case(f"paper_cylinder_re500_{label}", nx, ny, collision=collision, storage=storage,
+                tau=tau_from_reynolds(0.05, d, re), eta=eta, bc=bc, u_in=(0.05, 0.0),
+                u0=(0.05, 0.0), bodies=[body("disk", up, ny / 2.0, r=d / 2.0)],
+                steps=int(round(600_000 * scale)), diameter=d)
+
+
+def paper_cylinder_sensitivity(storage="f32") -> List[Case]:
+    """The variants of the Re = 500 study, the paper's own setup first."""
+    return [paper_cylinder_variant("base", storage),
+            paper_cylinder_variant("zero_gradient_outlet", storage, outlet=OUTFLOW),
+            paper_cylinder_variant("eta_1e-5", storage, eta=1e-5),
+            paper_cylinder_variant("eta_1e-3", storage, eta=1e-3),
+            paper_cylinder_variant("inlet_10d", storage, upstream=10.0),
+            paper_cylinder_variant("outlet_40d", storage, downstream=40.0),
+            paper_cylinder_variant("mrt", storage, collision=MRT),
+            paper_cylinder_variant("half_resolution", storage, scale=0.5),
+            paper_cylinder_variant("height_20d", storage, height=20.0),
+            paper_cylinder_variant("inlet_20d", storage, upstream=20.0),
+            paper_cylinder_variant("inlet_10d_height_20d", storage, upstream=10.0, height=20.0),
+            paper_cylinder_variant("half_resolution_mrt", storage, scale=0.5, collision=MRT)]
+
+
 # ---- random inputs for parity tests ---------------------------------------------------------
 
 def random_fields(nx: int, ny: int, seed: int, rho_amp=0.02, u_amp=0.03, u_mean=(0.0, 0.0)):

@@ -38,6 +38,7 @@ class SweepPoint:
     params: dict
     case: I.Case
     error_of: object      # callable(rho, ux, uy) -> float
+    other_errors: object = None   # callable(rho, ux, uy) -> dict of other error measures
 
 
 def shear_case(collision, tau, lam=0.375, steps=None, nx=64, storage="f64"):
@@ -58,13 +59,20 @@ def shear_case(collision, tau, lam=0.375, steps=None, nx=64, storage="f64"):
     return SweepPoint(case.name, {"collision": collision, "tau": tau, "lambda": lam}, case, err)
 
 
-def couette_case(collision, tau, lam, L=200, ngrid=25, ud=0.01, steps=None, storage="f64"):
+def couette_case(collision, tau, lam, L=200, ngrid=25, ud=0.01, steps=None, storage="f64",
+                 centre=None):
+    """Taylor-Couette flow (Eq. 21) between a disk turning at surface speed ud and a fixed ring,
+    centred at (centre, centre): (L - 1)/2 by default (reading R5 of the design notes), L/2 as an
+    alternative staircase.  Besides the L2 error of v over the fluid annulus (the measure of
+    Figs 11, 12 and 17), the point reports the same without the staircase layer (fluid nodes with
+    a solid neighbour), along the line y = L/2 of Fig. 13, and of the velocity vector."""
     steps = steps or relax_steps(ngrid, tau)
     R2 = 0.35 * L
     R1 = R2 - ngrid
-    c = (L - 1) / 2
+    c = (L - 1) / 2 if centre is None else centre
     bodies = [I.body("disk", c, c, r=R1, omega=ud / R1), I.body("disk_outside", c, c, r=R2)]
-    case = I.Case(f"couette_{collision}_L{L}_tau{tau:g}_lam{lam:g}", L, L, collision=collision,
+    tag = "" if centre is None else f"_c{c:g}"
+    case = I.Case(f"couette_{collision}_L{L}_tau{tau:g}_lam{lam:g}{tag}", L, L, collision=collision,
                   storage=storage, tau=tau, lam=lam, eta=1e-7, bc=I.ALL_PERIODIC, bodies=bodies,
                   steps=steps)
     yy, xx = np.mgrid[0:L, 0:L]
@@ -73,12 +81,27 @@ def couette_case(collision, tau, lam, L=200, ngrid=25, ud=0.01, steps=None, stor
     with np.errstate(divide="ignore", invalid="ignore"):
         ut = -ud * R1 * r / (R2 ** 2 - R1 ** 2) + ud * R1 * R2 ** 2 / ((R2 ** 2 - R1 ** 2) * r)  # Eq. 21
         vy = ut * dx / r
+        vx = -ut * dy / r
     fluid = (r > R1) & (r < R2)
+    near = np.zeros_like(fluid)
+    for ex in (-1, 0, 1):
+        for ey in (-1, 0, 1):
+            near |= np.roll(~fluid, (ey, ex), axis=(0, 1))
+    inner = fluid & ~near
+    line = np.zeros_like(fluid)
+    line[int(round(L / 2)), :] = True
+    line &= fluid
 
     def err(rho, ux, uy):
         return A.l2_error(uy, vy, fluid)
+
+    def others(rho, ux, uy):
+        return {"l2_v_without_staircase_layer": float(A.l2_error(uy, vy, inner)),
+                "l2_v_line_y_half": float(A.l2_error(uy, vy, line)),
+                "l2_vector": float(A.l2_error(np.stack([ux, uy]), np.stack([vx, vy]),
+                                              np.stack([fluid, fluid])))}
     return SweepPoint(case.name, {"collision": collision, "tau": tau, "lambda": lam, "L": L,
-                                  "Ngrid": ngrid}, case, err)
+                                  "Ngrid": ngrid, "centre": c}, case, err, others)
 
 
 def fig3_shear():
@@ -93,6 +116,21 @@ def fig12_couette():
     pts += [couette_case("mrt", 10.0, lam) for lam in (0.0005, 0.0016, 0.005, 0.02, 0.06, 0.1, 0.2,
                                                        0.375)]
     pts += [couette_case("srt", t, 0.0) for t in (0.7, 1.0, 10.0)]
+    return pts
+
+
+def fig12_readings(steps_scale=1):
+    """Readings of Fig. 12 at tau = 10 and 0.7: a dense Lambda sweep near zero, the disk centred
+    at (L - 1)/2 and at L/2, each point reporting every error measure of couette_case; with
+    steps_scale the runs go steps_scale times longer than the viscous relaxation estimate (at
+    tau = 10 and Lambda = 0.0016 the odd rate is 1.9993, whose non-hydrodynamic modes decay by
+    only 0.07% per step)."""
+    lams = (0.0005, 0.0016, 0.005, 0.01, 0.02, 0.04, 0.06, 0.08, 0.1, 0.14, 3 / 16, 0.375)
+    pts = []
+    for tau in (10.0, 0.7):
+        steps = relax_steps(25, tau) * steps_scale
+        for c in (None, 100.0):
+            pts += [couette_case("mrt", tau, lam, steps=steps, centre=c) for lam in lams]
     return pts
 
 
@@ -149,5 +187,7 @@ def run(points: List[SweepPoint], budget_bytes=8 << 30, max_slots=256, steps_per
                 out[rid] = {"label": p.label, **p.params, "l2_error": float(p.error_of(rho, ux, uy)),
                             "status": int(obs["status"]), "steps": int(done),
                             "residual": None if math.isinf(res) else float(res)}
+                if p.other_errors:
+                    out[rid].update(p.other_errors(rho, ux, uy))
     pool.close()
     return [out[r] for r in ids]

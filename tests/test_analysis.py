@@ -4,6 +4,7 @@ import math
 import numpy as np
 
 from paper_1812_05401_amd import analysis as A
+from paper_1812_05401_amd import inputs as I
 
 
 def test_strouhal_of_a_pure_sinusoid():
@@ -59,3 +60,24 @@ def test_spectral_strouhal_recovers_the_frequency_under_noise():
     for cl in (clean, noisy):
         assert abs(A.strouhal_spectral(cl, d, u) / st - 1) < 3e-3
     assert A.strouhal_spectral(np.zeros(100), d, u) is None
+
+
+def test_force_regions_add_up_to_the_next_steps_force():
+    """The surface / interior split of the penalization force (study.body_force_regions), taken
+    on a state, adds up to the force the oracle reduces in the next step."""
+    import oracle as O
+    from paper_1812_05401_amd import study
+    from tests.helpers import oracle_sim
+    case = I.cylinder_wake(160, 64, d=16.0, x0=40.0, re=100.0)
+    o = oracle_sim(case)
+    o.step(300)
+    r = study.body_force_regions(o.populations(), o.mask(), 1, case.eta)
+    o.step(1)
+    ob = o.obs()
+    sc = float(ob["fabs_sum"][0])
+    assert r["surface_nodes"] > 0 and r["interior_nodes"] > 0
+    assert abs(r["surface"][0] + r["interior"][0] - ob["fx"][0]) < 1e-12 * sc
+    assert abs(r["surface"][1] + r["interior"][1] - ob["fy"][0]) < 1e-12 * sc
+    assert abs(r["layers"][0][0] - r["surface"][0]) < 1e-14 * sc
+    assert abs(sum(l[0] for l in r["layers"]) - ob["fx"][0]) < 1e-12 * sc
+    assert sum(l[2] for l in r["layers"]) == r["surface_nodes"] + r["interior_nodes"]
