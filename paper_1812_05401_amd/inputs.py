@@ -148,7 +148,8 @@ def paper_cylinder_sensitivity(storage="f32") -> List[Case]:
             paper_cylinder_variant("height_20d", storage, height=20.0),
             paper_cylinder_variant("inlet_20d", storage, upstream=20.0),
             paper_cylinder_variant("inlet_10d_height_20d", storage, upstream=10.0, height=20.0),
-            paper_cylinder_variant("half_resolution_mrt", storage, scale=0.5, collision=MRT)]
+            paper_cylinder_variant("half_resolution_mrt", storage, scale=0.5, collision=MRT),
+            paper_cylinder_variant("inlet_20d_height_40d", storage, upstream=20.0, height=40.0)]
 
 
 # ---- random inputs for parity tests ---------------------------------------------------------

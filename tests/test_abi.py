@@ -110,3 +110,9 @@ def test_null_and_foreign_handles_are_rejected():
     assert lib.vplbm_pool_cancel(bogus, 0) == B.EINVAL
     assert lib.vplbm_pool_advance(None, None, None, None) == B.EINVAL
     assert "invalid pool" in B.last_error()
+
+
+def test_plain_16_bit_names_select_stochastic_rounding():
+    """"f16" and "bf16" are the stochastically rounded formats (the mass-keeping defaults)."""
+    assert B.STORAGE["f16"] == B.F16SR and B.STORAGE["bf16"] == B.BF16SR
+    assert B.make_config(8, 8, storage="bf16").storage == B.BF16SR
