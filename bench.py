@@ -21,7 +21,6 @@ GPU before timing starts.  `--copy-probe BYTES` instead times a plain device cop
 HBM ceiling and the calibration kernel for the FETCH_SIZE/WRITE_SIZE counters).
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,12 +38,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E datasheet peak
 VALU_FMA_RATE_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-def source_digest():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "lattice.hpp", "kernels.hpp", "runtime.hip"):
-        with open(os.path.join(ROOT, "paper_1812_05401_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+from paper_1812_05401_amd.counters import source_digest  # noqa: E402  (the counter tables carry it)
 
 
 def cache_resident(case):

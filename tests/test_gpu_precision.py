@@ -147,3 +147,74 @@ def test_f16sr_rounds_subnormal_values_on_their_quantum(gpu, steps, nt):
         two_valued += bool(np.any(down & ~up)) and bool(np.any(up & ~down))
         assert abs((h - h_ref).mean()) <= 5 * q * 0.5 / np.sqrt(h.size)
     assert two_valued >= 6
+
+
+@pytest.mark.parametrize("steps,nt", [(1, False), (1, True), (2, False), (2, True)],
+                         ids=["one_step", "one_step_nt", "two_step", "two_step_nt"])
+def test_f16sr_rounds_each_lane_of_a_mixed_wave_on_its_own_grid(gpu, steps, nt):
+    """Fluid at rest whose density alternates every 8 columns between about 1 + 1e-5 (seeded
+    per-node noise of +-50%, so the values spread over the grid) and 1 + 1e-2, so that every wave
+    holds lanes whose shifted populations lie below 2^-14 (binary16's subnormal
+    range, quantum 2^-24) beside lanes whose values lie above.  The wave-uniform branch that
+    redoes the small values must do so for every such lane of a wave: a small value rounded on the
+    path meant for normal values (random bits under the binary32 mantissa, then a round to nearest
+    in the conversion) is all but rounded to nearest at these magnitudes.  So, against the FP32
+    value of the same step: every small value lies on one of its two neighbours on the 2^-24
+    grid, and among the values at fractional position 0.1-0.4 (0.6-0.9) between them the share
+    rounded up matches the mean fraction to 5 standard errors, as stochastic rounding gives and
+    rounding to nearest (a share of 0, or 1) does not.  Large values lie within one binary16 ulp."""
+    import os
+    q = 2.0 ** -24
+    ny, nx = 96, 128
+    case = I.Case("sr_mixed", nx, ny, storage="f16sr", bc=I.ALL_PERIODIC, u0=(0.0, 0.0),
+                  tau=0.7)
+    rng = np.random.default_rng(11)
+    small_col = ((np.arange(nx) // 8) % 2 == 0)[None, :]
+    drho = np.where(small_col, 1e-5 * (1.0 + 0.5 * rng.uniform(-1.0, 1.0, (ny, nx))), 1e-2)
+    pop = W[:, None, None] * (1.0 + drho)[None]
+    old = os.environ.get("VPLBM_NT_STORE")
+    os.environ["VPLBM_NT_STORE"] = "1" if nt else "0"
+    try:
+        g = gpu_sim(case)
+    finally:
+        if old is None:
+            os.environ.pop("VPLBM_NT_STORE")
+        else:
+            os.environ["VPLBM_NT_STORE"] = old
+    g.set_populations(pop, 0)
+    before = g.populations()
+    if steps == 2:
+        pre = gpu_sim(case)                  # the state after the first step, one step per launch
+        pre.set_populations(pop, 0)
+        pre.step(1)
+        before = pre.populations()
+        pre.close()
+    ref = gpu_sim(case, storage="f32")
+    ref.set_populations(before, steps - 1)
+    g.step(steps)
+    ref.step(1)
+    got, want = g.populations(), ref.populations()
+    h_ref = (want - W[:, None, None]).ravel()
+    h = (got - W[:, None, None]).ravel()
+    a = np.abs(h_ref)
+    small = (a > 0) & (a < 0.99 * 2.0 ** -14)
+    large = a > 1.01 * 2.0 ** -14
+    assert small.sum() > 20000 and large.sum() > 30000
+    hs, rs = h[small], h_ref[small]
+    n = hs / q
+    assert np.all(np.abs(n - np.round(n)) < 1e-6)                   # on the subnormal grid
+    lo = np.floor(rs / q)
+    frac = rs / q - lo
+    up = np.abs(n - (lo + 1)) < 1e-3
+    assert np.all(up | (np.abs(n - lo) < 1e-3))
+    for a0, a1 in ((0.1, 0.4), (0.6, 0.9)):
+        sel = (frac >= a0) & (frac <= a1)
+        assert sel.sum() >= 500
+        p = frac[sel].mean()
+        share = up[sel].mean()
+        print(f"fraction {a0}-{a1}: {sel.sum()} values, mean {p:.3f}, rounded up {share:.3f}",
+              flush=True)
+        assert abs(share - p) <= 5 * np.sqrt(p * (1 - p) / sel.sum())
+    assert np.all(np.abs(h[large] - h_ref[large]) <= 2 * half_ulp(h_ref[large], 10))
+    g.close()
+    ref.close()
