@@ -41,6 +41,25 @@ VALU_FMA_RATE_T = 256 * 4 * 16 * 2.4e9 / 1e12
 from paper_1812_05401_amd.counters import source_digest  # noqa: E402  (the counter tables carry it)
 
 
+def pattern_ceilings(nx, ny, launches=64):
+    """The step kernels' access patterns with a trivial per-node update (libvplbm_probes.so) on an
+    nx x ny FP32 lattice: microseconds per launch with 1, 2 and 3 updates per launch (the one-step
+    kernel's 128 x 2 workgroups, the two-step kernel's 128 x 8 tiles, 128 x 6 tiles for three), the
+    best of three timings.  A probe needs the lattice to be a whole number of tiles: otherwise it
+    runs on the largest such lattice inside and its time is scaled by the node count.  The FP32 FMA issue rate of
+    independent chains comes with it."""
+    from paper_1812_05401_amd import probes as P
+    out = {"lattice": f"{nx}x{ny}", "storage": "f32", "bytes_per_node_per_launch": 73}
+    for spl, tile in ((1, (128, 2)), (2, (128, 8)), (3, (128, 6))):
+        nxt, nyt = nx - nx % tile[0], ny - ny % tile[1]
+        us = min(P.pattern_us(nxt, nyt, spl, tile, launches) for _ in range(3)) * (nx * ny) / (nxt * nyt)
+        out[f"steps_per_launch_{spl}"] = {"tile": list(tile), "us_per_launch": round(us, 2),
+                                          "us_per_step": round(us / spl, 2),
+                                          "gbs": round(73 * nx * ny / (us * 1e-6) / 1e9, 1)}
+    out["fma_lane_per_s_t"] = round(P.fma_rate(20) / 1e12, 3)
+    return out
+
+
 def cache_resident(case):
     """Whether the two population buffers fit in the 256 MB Infinity Cache."""
     eb = {"f64": 8, "f32": 4, "f32d": 4}.get(case.storage, 2)
@@ -306,6 +325,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the objects beside the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--probes", action="store_true",
+                    help="instead of the benchmark: the access-pattern ceilings (trivial per-node "
+                         "update) of the benchmark lattices and the FMA issue rate, one JSON line")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--precision-study", default="", metavar="WORKLOAD",
                     help="instead of the benchmark: run WORKLOAD (cylinder_wake_2048x512, "
@@ -354,6 +376,10 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(args.copy_probe, max(args.steps, 1))
+        return
+    if args.probes:
+        res = {"probes": [pattern_ceilings(nx, ny) for nx, ny in ((8192, 2048), (2048, 512), (6048, 2016))]}
+        print(json.dumps(res), flush=True)
         return
 
     from paper_1812_05401_amd import binding as B
@@ -438,7 +464,16 @@ def main():
         "steps_per_launch": main_res["steps_per_launch"],
         "one_step_equivalent_gbs": main_res["one_step_equivalent_gbs"],
     }
-    if main_res["steps_per_launch"] == 2:
+    if not args.no_extra:
+        # the same access pattern with a trivial update: the ceiling of the pattern itself
+        pc = pattern_ceilings(case.nx, case.ny)
+        line["pattern_ceilings"] = pc
+        ceil = pc.get(f"steps_per_launch_{main_res['steps_per_launch']}")
+        if ceil:
+            line["roofline"]["pattern_ceiling_us"] = ceil["us_per_launch"]
+            line["roofline"]["frac_of_pattern_ceiling"] = round(
+                ceil["us_per_launch"] / line["roofline"]["launch_us"], 4)
+    if main_res["steps_per_launch"] >= 2:
         # the same workload with one step per launch: the memory-bound kernel and its roofline
         one = time_workload(workloads[args.workload](), args.steps, args.warmup,
                             storage=args.storage or None, two_step=False)

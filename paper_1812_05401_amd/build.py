@@ -1,4 +1,5 @@
-"""Build the HIP library libvplbm.so for gfx950 (MI355X) in-tree.
+"""Build the HIP library libvplbm.so and the measurement probes libvplbm_probes.so for gfx950
+(MI355X) in-tree.
 
     python -m paper_1812_05401_amd.build [-v]
 
@@ -17,6 +18,10 @@ SOURCES = [os.path.join(CSRC, f) for f in ("kernels.hip", "runtime.hip", "pool.h
 HEADERS = [os.path.join(CSRC, f) for f in ("kernels.hpp", "lattice.hpp", "internal.hpp", "pool_policy.hpp", "step_plan.hpp", "static_scratch.hpp")] + [
     os.path.join(INCLUDE, "vplbm.h")]
 ARCH = os.environ.get("VPLBM_OFFLOAD_ARCH", "gfx950")
+# The probes: the step's access patterns with a trivial update, a copy, FMA chains (bench.py).
+PROBE_LIB = os.path.join(PKG, "libvplbm_probes.so")
+PROBE_SOURCES = [os.path.join(CSRC, "probes.hip")]
+PROBE_HEADERS = [os.path.join(CSRC, "lattice.hpp"), os.path.join(INCLUDE, "vplbm_probes.h")]
 
 
 def hipcc():
@@ -25,15 +30,21 @@ def hipcc():
     return path if os.path.exists(path) else "hipcc"
 
 
-def command(out=LIB):
+def command(out=LIB, sources=None):
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             "-munsafe-fp-atomics", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-I", INCLUDE, "-I", CSRC, "-o", out] + SOURCES
+            "-Wall", "-I", INCLUDE, "-I", CSRC, "-o", out] + (sources or SOURCES)
 
 
 def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+    _compile(LIB, SOURCES, verbose)
+    _compile(PROBE_LIB, PROBE_SOURCES, verbose)
+    return LIB
+
+
+def _compile(lib, sources, verbose):
+    tmp = lib + ".tmp"
+    cmd = command(tmp, sources)
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,15 +55,17 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 def stale() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in SOURCES + HEADERS)
+    for lib, deps in ((LIB, SOURCES + HEADERS), (PROBE_LIB, PROBE_SOURCES + PROBE_HEADERS)):
+        if not os.path.exists(lib):
+            return True
+        t = os.path.getmtime(lib)
+        if any(os.path.getmtime(p) > t for p in deps):
+            return True
+    return False
 
 
 if __name__ == "__main__":

@@ -116,3 +116,24 @@ def test_plain_16_bit_names_select_stochastic_rounding():
     """"f16" and "bf16" are the stochastically rounded formats (the mass-keeping defaults)."""
     assert B.STORAGE["f16"] == B.F16SR and B.STORAGE["bf16"] == B.BF16SR
     assert B.make_config(8, 8, storage="bf16").storage == B.BF16SR
+
+
+def test_probe_library_exports_its_header():
+    """libvplbm_probes.so (the measurement probes bench.py times) exports every call
+    include/vplbm_probes.h declares and rejects bad arguments before any device work."""
+    from paper_1812_05401_amd import probes as P
+    text = open(os.path.join(os.path.dirname(HEADER), "vplbm_probes.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(vplbm_probe_[a-z_0-9]+)\s*\(", text)))
+    assert len(names) == 4
+    lib = P.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    out = C.c_double()
+    assert lib.vplbm_probe_pattern(8192, 2048, 2, 100, 8, 10, C.byref(out)) == -1
+    assert "no probe" in P.load().vplbm_probe_last_error().decode()
+    assert lib.vplbm_probe_pattern(1000, 2048, 2, 128, 8, 10, C.byref(out)) == -1
+    assert lib.vplbm_probe_pattern(8192, 2048, 1, 128, 2, 0, C.byref(out)) == -1
+    assert lib.vplbm_probe_copy(1000, 5, C.byref(out)) == -1
+    assert lib.vplbm_probe_fma(0, C.byref(out)) == -1
+    assert lib.vplbm_probe_fma(5, None) == -1
