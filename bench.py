@@ -86,10 +86,10 @@ def measured_traffic(workload, storage, steps_per_launch=1):
     return ent and ent.get("bytes_per_launch")
 
 
-def time_workload(case, steps, warmup, storage=None, two_step=True):
-    """Time `steps` steps of `case` after `warmup`.  two_step=False creates the simulation with
-    one step per launch (VPLBM_TWO_STEP=0); otherwise the library takes two steps per launch where
-    the case allows it."""
+def time_workload(case, steps, warmup, storage=None, spl=3):
+    """Time `steps` steps of `case` after `warmup`, with at most `spl` steps per launch: 1 creates
+    the simulation with VPLBM_TWO_STEP=0, 2 with VPLBM_THREE_STEP=0; the library takes as many as
+    the case allows (three for binary32 storage without a convective outlet, else two)."""
     import torch
     from paper_1812_05401_amd import binding as B
     if storage:
@@ -99,15 +99,17 @@ def time_workload(case, steps, warmup, storage=None, two_step=True):
     # reads as "use a stream of your own").
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    old = os.environ.get("VPLBM_TWO_STEP")
-    os.environ["VPLBM_TWO_STEP"] = "1" if two_step else "0"
+    want = {"VPLBM_TWO_STEP": "1" if spl >= 2 else "0", "VPLBM_THREE_STEP": "1" if spl >= 3 else "0"}
+    old = {k: os.environ.get(k) for k in want}
+    os.environ.update(want)
     try:
         sim = B.Simulation(case, stream=int(stream.cuda_stream))
     finally:
-        if old is None:
-            os.environ.pop("VPLBM_TWO_STEP")
-        else:
-            os.environ["VPLBM_TWO_STEP"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k)
+            else:
+                os.environ[k] = v
     assert sim.stream == stream.cuda_stream
     spl = sim.steps_per_launch
     sim.step(warmup)
@@ -129,17 +131,18 @@ def time_workload(case, steps, warmup, storage=None, two_step=True):
     # One launch updates every node spl times (the graph's step-counter kernel, one per 128 steps,
     # and, with moving bodies, the kernel that rebuilds their masks before each launch are included
     # in the launch time).  The bytes it moves are one read and one write of the planes plus the
-    # mask whatever spl is: the two-step kernel keeps the intermediate step on chip.
+    # mask whatever spl is: the multi-step kernels keep the intermediate steps on chip.
     launch_s = gpu_ms / 1e3 / steps * spl
-    # moving bodies: a two-step launch reads the masks of both of its steps (1 B per node more)
+    # moving bodies: a launch of several steps reads the mask of each of its steps (1 B per node
+    # and step more)
     moving = any(b["freq"] != 0 and (b["ax"] != 0 or b["ay"] != 0) for b in case.bodies)
-    bytes_launch = (bpu + (1 if spl == 2 and moving else 0)) * case.nodes
+    bytes_launch = (bpu + (spl - 1 if moving else 0)) * case.nodes
     hbm = bytes_launch / launch_s / 1e9
     # The per-update figure: bpu bytes (9 loads, 9 stores, the mask) for each of the spl lattice
-    # updates of a launch, over the same launch time.  Above 1 for the two-step kernel, which
-    # moves those bytes once per two updates.
+    # updates of a launch, over the same launch time.  Above 1 for the multi-step kernels, which
+    # move those bytes once per spl updates.
     per_update = bpu * spl * case.nodes / launch_s / 1e9
-    kernel = "vplbm::step2_kernel" if spl == 2 else "vplbm::step_kernel"
+    kernel = {1: "vplbm::step_kernel", 2: "vplbm::step2_kernel", 3: "vplbm::step3_kernel"}[spl]
     roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(hbm / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(case.name, case.storage, spl),
@@ -474,11 +477,20 @@ def main():
             line["roofline"]["frac_of_pattern_ceiling"] = round(
                 ceil["us_per_launch"] / line["roofline"]["launch_us"], 4)
     if main_res["steps_per_launch"] >= 2:
-        # the same workload with one step per launch: the memory-bound kernel and its roofline
-        one = time_workload(workloads[args.workload](), args.steps, args.warmup,
-                            storage=args.storage or None, two_step=False)
-        line["one_step_per_launch"] = {k: one[k] for k in ("mlups", "ms_per_step", "roofline")}
-        print(f"# {case.name} one step per launch: {one['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        # the same workload with fewer steps per launch: one (the memory-bound kernel and its
+        # roofline) and, under three, two
+        for spl, key in ((2, "two_steps_per_launch"), (1, "one_step_per_launch")):
+            if spl >= main_res["steps_per_launch"]:
+                continue
+            r = time_workload(workloads[args.workload](), args.steps, args.warmup,
+                              storage=args.storage or None, spl=spl)
+            line[key] = {k: r[k] for k in ("mlups", "ms_per_step", "roofline")}
+            c = pc.get(f"steps_per_launch_{spl}") if not args.no_extra else None
+            if c:
+                line[key]["roofline"]["pattern_ceiling_us"] = c["us_per_launch"]
+                line[key]["roofline"]["frac_of_pattern_ceiling"] = round(
+                    c["us_per_launch"] / line[key]["roofline"]["launch_us"], 4)
+            print(f"# {case.name} {spl} step(s) per launch: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     if not args.no_extra:
         # the 2048 x 512 wake: buffers inside the Infinity Cache, so MLUPS only
         c2 = I.cylinder_wake_2048x512()
@@ -504,14 +516,14 @@ def main():
             print(f"# {c.name}/{st}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         line["reduced_precision"] = {"workload": "cylinder_wake_8192x2048", **red}
         # the paper's own Re = 500 cylinder (6048 x 2016, SRT, convective outlet), FP32
-        pc = {}
+        pcr = {}
         for two in (True, False):
-            r = time_workload(I.paper_cylinder_re500("f32"), 400, 40, two_step=two)
-            pc["two_steps_per_launch" if two else "one_step_per_launch"] = {
+            r = time_workload(I.paper_cylinder_re500("f32"), 400, 40, spl=2 if two else 1)
+            pcr["two_steps_per_launch" if two else "one_step_per_launch"] = {
                 k: r[k] for k in ("mlups", "ms_per_step", "steps_per_launch", "roofline")}
             print(f"# paper_cylinder_re500 ({'two' if two else 'one'} per launch): {r['mlups']:.0f} MLUPS",
                   file=sys.stderr, flush=True)
-        line["paper_cylinder_re500"] = {"workload": "paper_cylinder_re500", "storage": "f32", **pc}
+        line["paper_cylinder_re500"] = {"workload": "paper_cylinder_re500", "storage": "f32", **pcr}
         # FP32 square channels from cache-resident to far beyond the 256 MB Infinity Cache
         sweep = []
         for n, steps in ((2048, 400), (4096, 200), (8192, 60)):

@@ -20,40 +20,43 @@ __device__ __forceinline__ double *acc_set(const StepArgs &a, long long t)
     return a.acc + (size_t)(t & (kAccSets - 1)) * kSub * kRingWidth;
 }
 
-// Sum value q of the sub-slots of steps t - 2 and t - 1 (those that exist) into their ring
+// Sum value q of the sub-slots of steps t - kMaxSteps .. t - 1 (those that exist) into their ring
 // entries, with one wave: lane l adds sub-slots l, l + 64, ... in order, then a fixed butterfly
 // adds the lanes, so a result does not depend on which workgroup folds or when.  One memory round
-// trip for both steps.  Nothing is cleared, so folding a step again gives the same value: a step
-// is folded by the next launch and, when that launch starts one step later, by the one after.
-// The fold always takes the shuffle form of the wave sum, so that every fold of a step (by either
+// trip for all of them.  Nothing is cleared, so folding a step again gives the same value: a step
+// is folded by the next launch, and again by later ones while it is among their last kMaxSteps.
+// The fold always takes the shuffle form of the wave sum, so that every fold of a step (by any
 // kernel class, or by an observation) writes the same value.
 __device__ __forceinline__ void fold_recent(const StepArgs &a, long long t, int q)
 {
     const int lane = threadIdx.x & 63;
-    const double *s1 = acc_set(a, t - 1), *s2 = acc_set(a, t - 2);
-    double v1 = 0.0, v2 = 0.0;
+    double v[kMaxSteps];
+#pragma unroll
+    for (int d = 0; d < kMaxSteps; d++) v[d] = 0.0;
     for (int b = lane; b < kSub; b += 64) {
-        v1 += s1[b * kRingWidth + q];
-        v2 += s2[b * kRingWidth + q];
+#pragma unroll
+        for (int d = 0; d < kMaxSteps; d++) v[d] += acc_set(a, t - 1 - d)[b * kRingWidth + q];
     }
-    v1 = wave_sum<false>(v1);
-    v2 = wave_sum<false>(v2);
-    if (lane == 0) {
-        if (t >= 1) a.ring[(size_t)((t - 1) % a.ring_len) * kRingWidth + q] = v1;
-        if (t >= 2) a.ring[(size_t)((t - 2) % a.ring_len) * kRingWidth + q] = v2;
+#pragma unroll
+    for (int d = 0; d < kMaxSteps; d++) {
+        const double sum = wave_sum<false>(v[d]);
+        if (lane == 0 && t >= 1 + d) a.ring[(size_t)((t - 1 - d) % a.ring_len) * kRingWidth + q] = sum;
     }
 }
 
-// Start of a launch that computes steps t .. t + n - 1 (n = 1 or 2): workgroup q's first wave
-// folds value q of steps t - 2 and t - 1, and workgroup b zeroes sub-slot b of the sets of steps
-// t + n and t + n + 1, which the next launch accumulates into.  With kAccSets = 8, the sets
-// folded, written and cleared by one launch are distinct, and a set is cleared only after every
-// fold of its previous step (its launch and the next two have run).
+// Start of a launch that computes steps t .. t + n - 1 (1 <= n <= kMaxSteps): workgroup q's first
+// wave folds value q of steps t - kMaxSteps .. t - 1, and workgroup b zeroes sub-slot b of the
+// sets of steps t + n .. t + n + kMaxSteps - 1, which the next launch accumulates into.  The sets
+// one launch folds, writes and clears span at most 3 kMaxSteps consecutive steps, so with
+// kAccSets >= 3 kMaxSteps they are distinct.  Step s is first folded by a launch starting at most
+// kMaxSteps steps after s; the launch that clears its set for step s + kAccSets starts at least
+// kAccSets - 2 kMaxSteps + 1 steps after s, later in stream order, so every fold of s sees its
+// complete sums.
 __device__ __forceinline__ void reduction_prologue(const StepArgs &a, long long t, int n)
 {
     if (threadIdx.x < 64)
         for (int q = blockIdx.x; q < kRingWidth; q += gridDim.x) fold_recent(a, t, q);
-    if (threadIdx.x < 2 * kRingWidth) {
+    if (threadIdx.x < kMaxSteps * kRingWidth) {
         double *set = acc_set(a, t + n + threadIdx.x / kRingWidth);
         const int q = threadIdx.x % kRingWidth;
         for (int b = blockIdx.x; b < kSub; b += gridDim.x) set[b * kRingWidth + q] = 0.0;
@@ -277,6 +280,191 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
     }
 }
 
+// ---- three steps per launch --------------------------------------------------------------------
+// Steps t, t + 1 and t + 2 of a TW x TH tile in one launch.  Phase 1 computes step t on the tile
+// and a two-node halo from the planes in global memory into LDS; phase 2 computes step t + 1 on
+// the tile and a one-node halo from LDS, keeps its results in registers until every thread has
+// made its pulls, then writes them over the same slots; phase 3 computes step t + 2 of the tile
+// from LDS and stores it.  Each node's arithmetic is the one-step kernel's and every value kept in
+// LDS is rounded as a store to global memory would round it, so the populations are bitwise those
+// of three one-step launches, with one read and one write of the planes per three updates.  A halo
+// position across a periodic edge holds the wrapped node; one beyond a non-periodic edge or a
+// ragged tile is skipped (no later pull reads it).  The phases take the masks and body states of
+// their own steps (a.mask, a.mask2, a.mask3).  There is no convective outlet here: the host uses
+// the two-step kernel for it.  Tiles: 128 x 6 for binary32 (46 KB of LDS, three workgroups per
+// CU; the phases cover 1320, 1040 and 768 nodes).  Inner tiles load and the last phase stores
+// through buffer resources (pull_interior_buf, store_node_buf), which keep the plane offsets out
+// of the vector ALUs.
+template <int S, int TW, int TH, bool NT>
+__global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    using E = typename C::elem;
+    constexpr int EW = TW + 4, EN = EW * (TH + 4);       // phase 1: the tile and two halo rings
+    constexpr int MW = TW + 2, MN = MW * (TH + 2);       // phase 2: the tile and one halo ring
+    constexpr int NW = kBlock2 / 64;
+    constexpr int R1 = (EN + kBlock2 - 1) / kBlock2;
+    constexpr int R2 = (MN + kBlock2 - 1) / kBlock2;
+    constexpr int R3 = (TW * TH + kBlock2 - 1) / kBlock2;
+    constexpr bool MF = false;   // mask byte after the populations (mask first: 87 VGPRs without NT)
+    constexpr bool DPP = wave_sum_dpp<T>();
+    __shared__ E mid[9 * EN];                           // steps t, then t + 1, on the tile
+    __shared__ double wave_acc[3][NW][kRingWidth];      // per-wave partials of the three steps
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long long t = *a.t_base + a.t_off;
+    const Geom &g = a.g;
+    if (a.reduce) {
+        if (lane < kRingWidth)
+            for (int k = 0; k < 3; k++) wave_acc[k][wave][lane] = 0.0;
+        reduction_prologue(a, t, 3);
+    }
+    const int ntx = (g.nx + TW - 1) / TW;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % ntx) * TW, y0 = (tile / ntx) * TH;
+    const E *__restrict__ src = static_cast<const E *>(a.src);
+    // the source and destination planes as buffers (the host keeps three-step lattices below 4 GB)
+    const unsigned bytes = 9u * unsigned(g.plane) * unsigned(sizeof(E));
+    const __amdgpu_buffer_rsrc_t rsrc = buffer_over(const_cast<void *>(a.src), bytes);
+    const __amdgpu_buffer_rsrc_t rdst = buffer_over(a.dst, bytes);
+    const Outlet none{nullptr, nullptr, 0.0};
+    bool bad = false;
+    double mass = 0.0;
+    // A tile three or more nodes from every edge: every node of every phase pulls by plain shifts
+    // and needs no wrap.
+    const bool inner = (x0 >= 3) & (x0 + TW + 3 <= g.nx) & (y0 >= 3) & (y0 + TH + 3 <= g.ny);
+    // The lattice node at unwrapped position (ux, uy), h or fewer nodes outside the tile: live
+    // unless beyond a non-periodic edge or more than h beyond the lattice (a ragged tile).
+    auto locate = [&](int ux, int uy, int h, int &x, int &y) -> bool {
+        x = ux;
+        y = uy;
+        bool live = true;
+        if (x < 0 || x >= g.nx) {
+            if (g.xper && x >= -h && x < g.nx + h) x += x < 0 ? g.nx : -g.nx;
+            else live = false;
+        }
+        if (y < 0 || y >= g.ny) {
+            if (g.yper && y >= -h && y < g.ny + h) y += y < 0 ? g.ny : -g.ny;
+            else live = false;
+        }
+        return live;
+    };
+    auto in_tile = [&](int ux, int uy) -> bool {
+        return (ux >= x0) & (ux < x0 + TW) & (uy >= y0) & (uy < y0 + TH) & (ux < g.nx) & (uy < g.ny);
+    };
+
+    // Phase 1: step t.
+    for (int it = 0; it < R1; it++) {
+        const int e = threadIdx.x + it * kBlock2;
+        const int ux = x0 + e % EW - 2, uy = y0 + e / EW - 2;
+        int x = ux, y = uy;
+        const bool live = (e < EN) && (inner || locate(ux, uy, 2, x, y));
+        double fx_d = 0.0, fy_d = 0.0;
+        int id = 0;
+        if (live) {
+            if constexpr (MF) id = *at(a.mask, unsigned(y * g.pitch + x));
+            T f[9];
+            if (inner) pull_interior_buf<S>(rsrc, g.plane, g.pitch, unsigned(y * g.pitch + x), f);
+            else pull<S>(src, x, y, g, none, f);
+            const Macro<T> m = MF ? relax_node_id(f, id, a.bodies, g, a.p, x, y)
+                                  : relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
+            store_node<S>(mid, EN, unsigned(e), f, unsigned(y * g.pitch + x), (unsigned)t);
+            if (in_tile(ux, uy)) {
+                const double rho_d = 1.0 + double(m.drho);
+                mass += rho_d;
+                fx_d = double(m.fx);
+                fy_d = double(m.fy);
+                bad |= !(rho_d > 0.0 && rho_d < 1e30);
+            } else {
+                id = 0;                           // another tile's node: not in this tile's sums
+            }
+        }
+        if (a.reduce) wave_forces<DPP>(wave_acc[0][wave], fx_d, fy_d, id);
+    }
+    if (a.reduce) {
+        const double mw = wave_sum<DPP>(mass);
+        if (lane == 0) wave_acc[0][wave][0] = mw;
+    }
+    mass = 0.0;
+    __syncthreads();                              // the tile of step t is complete
+    if (a.reduce) add_partials(a, t, &wave_acc[0][0][0], NW);
+
+    // Phase 2: step t + 1, from LDS into registers, then over the same slots.
+    T res[R2][9];
+    int slot[R2];                                 // -1: no node
+    unsigned node[R2];
+#pragma unroll
+    for (int it = 0; it < R2; it++) {
+        const int j = threadIdx.x + it * kBlock2;
+        const int ux = x0 + j % MW - 1, uy = y0 + j / MW - 1;
+        int x = ux, y = uy;
+        const bool live = (j < MN) && (inner || locate(ux, uy, 1, x, y));
+        slot[it] = live ? (j / MW + 1) * EW + j % MW + 1 : -1;
+        node[it] = unsigned(y * g.pitch + x);
+        double fx_d = 0.0, fy_d = 0.0;
+        int id = 0;
+        if (live) {
+            if constexpr (MF) id = *at(a.mask2, node[it]);
+            if (inner) pull_tile_shifts<S, 2>(mid, EN, EW, ux, uy, x0, y0, res[it]);
+            else pull_tile<S, 2>(mid, EN, EW, ux, uy, x0, y0, g, res[it]);
+            const Macro<T> m = MF ? relax_node_id(res[it], id, a.bodies2, g, a.p, x, y)
+                                  : relax_node(res[it], a.mask2, a.bodies2, g, a.p, x, y, id);
+            if (in_tile(ux, uy)) {
+                const double rho_d = 1.0 + double(m.drho);
+                mass += rho_d;
+                fx_d = double(m.fx);
+                fy_d = double(m.fy);
+                bad |= !(rho_d > 0.0 && rho_d < 1e30);
+            } else {
+                id = 0;
+            }
+        }
+        if (a.reduce) wave_forces<DPP>(wave_acc[1][wave], fx_d, fy_d, id);
+    }
+    if (a.reduce) {
+        const double mw = wave_sum<DPP>(mass);
+        if (lane == 0) wave_acc[1][wave][0] = mw;
+    }
+    mass = 0.0;
+    __syncthreads();                              // every phase-2 pull has read step t
+    if (a.reduce) add_partials(a, t + 1, &wave_acc[1][0][0], NW);
+#pragma unroll
+    for (int it = 0; it < R2; it++)
+        if (slot[it] >= 0) store_node<S>(mid, EN, unsigned(slot[it]), res[it], node[it], (unsigned)(t + 1));
+    __syncthreads();                              // the tile of step t + 1 is complete
+
+    // Phase 3: step t + 2 of the tile, to global memory.
+#pragma unroll
+    for (int it = 0; it < R3; it++) {
+        const int j = threadIdx.x + it * kBlock2;
+        const int x = x0 + j % TW, y = y0 + j / TW;
+        double fx_d = 0.0, fy_d = 0.0;
+        int id = 0;
+        if ((j < TW * TH) & (x < g.nx) & (y < g.ny)) {
+            if constexpr (MF) id = *at(a.mask3, unsigned(y * g.pitch + x));
+            T f[9];
+            if (inner) pull_tile_shifts<S, 2>(mid, EN, EW, x, y, x0, y0, f);
+            else pull_tile<S, 2>(mid, EN, EW, x, y, x0, y0, g, f);
+            const Macro<T> m = MF ? relax_node_id(f, id, a.bodies3, g, a.p, x, y)
+                                  : relax_node(f, a.mask3, a.bodies3, g, a.p, x, y, id);
+            store_node_buf<S, NT>(rdst, g.plane, y * g.pitch + x, f);
+            const double rho_d = 1.0 + double(m.drho);
+            mass += rho_d;
+            fx_d = double(m.fx);
+            fy_d = double(m.fy);
+            bad |= !(rho_d > 0.0 && rho_d < 1e30);
+        }
+        if (a.reduce) wave_forces<DPP>(wave_acc[2][wave], fx_d, fy_d, id);
+    }
+    if (a.reduce) {
+        const double mw = wave_sum<DPP>(mass);
+        if (lane == 0) wave_acc[2][wave][0] = mw;
+        if (__ballot(bad) && lane == 0) atomicOr(a.status, 1u);
+        __syncthreads();
+        add_partials(a, t + 2, &wave_acc[2][0][0], NW);
+    }
+}
+
 __global__ void fold_kernel(StepArgs a)
 {
     const long long t = *a.t_base;
@@ -347,6 +535,18 @@ static void launch2(const StepArgs &a, hipStream_t st)
         if (a.nt_store) step2_kernel<S, TW, TH, true, false><<<grid, block, 0, st>>>(a);
         else step2_kernel<S, TW, TH, false, false><<<grid, block, 0, st>>>(a);
     }
+}
+
+bool step3_supported(int storage) { return storage == kF32; }
+
+hipError_t launch_step3(int storage, const StepArgs &a, hipStream_t st)
+{
+    constexpr int TW = 128, TH = 6;
+    if (storage != kF32 || a.outlet.prev) return hipErrorInvalidValue;
+    const dim3 grid(((a.g.nx + TW - 1) / TW) * ((a.g.ny + TH - 1) / TH)), block(kBlock2);
+    if (a.nt_store) step3_kernel<kF32, TW, TH, true><<<grid, block, 0, st>>>(a);
+    else step3_kernel<kF32, TW, TH, false><<<grid, block, 0, st>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st)
@@ -690,14 +890,14 @@ __global__ __launch_bounds__(kBlock) void mask_kernel(uint8_t *mask, Geom g, con
     mask[y * g.pitch + x] = rasterize_node(x, y, p, s, nb);
 }
 
-// Moving bodies before a launch of a.nsteps (1 or 2) steps: for each step s, the body states at
+// Moving bodies before a launch of a.nsteps (1 to 3) steps: for each step s, the body states at
 // time *t_base + t_off + s into a.state[s] and the swept boxes of the moving bodies re-rasterized
 // into a.mask[s], in one launch.  Every workgroup computes the states it needs into LDS (a few
 // FP64 sines per body); workgroup 0 also stores them.  The box nodes of all steps are spread over
 // the grid.  Boxes may overlap: such a node is written more than once with the same id.
 __global__ __launch_bounds__(kBlock) void place_kernel(PlaceArgs a)
 {
-    __shared__ BodyState st[2][kMaxBodies];
+    __shared__ BodyState st[kMaxSteps][kMaxBodies];
     __shared__ BodyParams bp[kMaxBodies];
     const int nb = a.nbodies;
     if ((int)threadIdx.x < nb) bp[threadIdx.x] = a.params[threadIdx.x];

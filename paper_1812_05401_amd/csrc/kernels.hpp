@@ -16,9 +16,12 @@ constexpr int kBlock2 = 512;                     // the two-step kernel's workgr
 // b % kSub, so no address takes more than 1/kSub of the atomics (device-scope FP64 atomics to
 // one address serialize).  The next launch's first workgroups (or the fold kernel at observation
 // time) sum the sub-slots in a fixed order into the ring.  Steps use kAccSets sets of sub-slots
-// round-robin, so that a two-step launch can fold the steps before it while it adds into its own.
+// round-robin, so that a launch of up to kMaxSteps steps can fold the kMaxSteps steps before it
+// while it adds into its own and clears those of the next launch.
 constexpr int kSub = 64;
-constexpr int kAccSets = 8;
+constexpr int kMaxSteps = 3;                     // steps per launch, at most
+constexpr int kAccSets = 16;                     // >= 3 kMaxSteps, a power of two
+static_assert(kAccSets >= 3 * kMaxSteps && (kAccSets & (kAccSets - 1)) == 0, "reduction sets");
 
 struct BodyParams {          // as given by the caller (vplbm_body), device copy
     int kind;                // 0 disk, 1 rect, 2 outside of a disk
@@ -31,8 +34,10 @@ struct StepArgs {
     void *dst;               // planes this step writes
     const uint8_t *mask;     // body id per node (pitch = geometry pitch)
     const BodyState *bodies; // body state at this step's time
-    const uint8_t *mask2;    // two-step launches: mask and body states of the second step (the
-    const BodyState *bodies2;//   same arrays as mask / bodies unless bodies move)
+    const uint8_t *mask2;    // two- and three-step launches: mask and body states of the second
+    const BodyState *bodies2;//   step (the same arrays as mask / bodies unless bodies move)
+    const uint8_t *mask3;    // three-step launches: those of the third step
+    const BodyState *bodies3;
     double *ring;            // [ring_len][kRingWidth] per-step observables
     double *acc;             // [kAccSets][kSub][kRingWidth] per-step partial sums
     unsigned *status;        // bit 0: non-finite or non-positive density seen
@@ -58,6 +63,10 @@ hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st);
 // Steps *t_base + t_off and the one after in one launch, from a.src into a.dst; the second step
 // takes its mask and body states from a.mask2 / a.bodies2 (no convective outlet).
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st);
+// Steps *t_base + t_off .. + 2 in one launch (binary32 storage without a convective outlet); the
+// second and third steps take a.mask2 / a.bodies2 and a.mask3 / a.bodies3.
+bool step3_supported(int storage);
+hipError_t launch_step3(int storage, const StepArgs &a, hipStream_t st);
 
 // Per-node density and penalized velocity of the current state into dense FP64 arrays.
 hipError_t launch_readback(int storage, const StepArgs &a, double *rho, double *ux, double *uy,
@@ -76,7 +85,7 @@ hipError_t launch_decode(int storage, const StepArgs &a, double *pop, hipStream_
 hipError_t launch_bodies(const BodyParams *params, BodyState *state, int nbodies,
                          const long long *t_base, int t_off, hipStream_t st);
 
-// Moving bodies before a launch of nsteps (1 or 2) steps, in one launch: for step s of the launch
+// Moving bodies before a launch of nsteps (1 to 3) steps, in one launch: for step s of the launch
 // (time *t_base + t_off + s) the body states into state[s] and the swept boxes re-rasterized into
 // mask[s].  box[k] = (x0, y0, w, h) of body k (w = 0: none, e.g. a static body); box_start holds
 // the prefix sums of the box areas (box_start[kMaxBodies] = all of them).  Every box lies inside
@@ -85,8 +94,8 @@ struct PlaceArgs {
     const BodyParams *params;
     int nbodies;
     int nsteps;
-    uint8_t *mask[2];
-    BodyState *state[2];
+    uint8_t *mask[kMaxSteps];
+    BodyState *state[kMaxSteps];
     const long long *t_base;
     int t_off;
     Geom g;

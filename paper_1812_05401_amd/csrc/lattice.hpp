@@ -303,7 +303,10 @@ __device__ __forceinline__ void pull(const typename Codec<S>::elem *__restrict__
 }
 
 // Element of a workgroup's LDS tile (see pull_tile) that direction a of node (x, y) pulls from,
-// and its plane in pa: edge_source without the periodic wrap, which the tile's halo holds.
+// and its plane in pa: edge_source without the periodic wrap, which the tile's halo holds.  The
+// tile starts H nodes before the workgroup's first node (x0, y0) in both directions; (x, y) are
+// unwrapped coordinates (a halo node across a periodic edge lies outside the lattice).
+template <int H = 1>
 __device__ __forceinline__ unsigned tile_source(int a, int x, int y, int x0, int y0, int ew,
                                                 const Geom &g, int &pa)
 {
@@ -314,25 +317,25 @@ __device__ __forceinline__ unsigned tile_source(int a, int x, int y, int x0, int
     pa = a;
     if ((sy < 0 || sy >= g.ny) && !g.yper) { sy = y; pa = mirror_y[a]; }
     if ((sx < 0 || sx >= g.nx) && !g.xper) sx = sx < 0 ? 0 : g.nx - 1;
-    return unsigned((sy - y0 + 1) * ew + (sx - x0 + 1));
+    return unsigned((sy - y0 + H) * ew + (sx - x0 + H));
 }
 
 // Pull the nine shifted populations h of node (x, y) from a workgroup's tile in LDS instead of the
 // planes in global memory.  The tile holds the post-collision populations of the nodes
-// [x0 - 1, x0 + ew - 2] x [y0 - 1, ...] in unwrapped coordinates, ew per row, `plane` elements
+// [x0 - H, x0 + ew - H - 1] x [y0 - H, ...] in unwrapped coordinates, ew per row, `plane` elements
 // per population: a periodic neighbour across an edge sits in the tile's halo, so for the tile
 // only the free-slip and clamped edges of edge_source remain.  Every node the pull reads lies
 // within one node of (x, y), inside the tile.
 // The tile pull of a node whose nine sources are plain shifts (no free-slip or clamped edge next to
 // it): every index below is >= 0, the tile having a halo.
-template <int S>
+template <int S, int H = 1>
 __device__ __forceinline__ void pull_tile_shifts(const typename Codec<S>::elem *tile, unsigned plane,
                                                  int ew, int x, int y, int x0, int y0,
                                                  typename Codec<S>::real f[9])
 {
     using C = Codec<S>;
     using T = typename C::real;
-    const unsigned e = unsigned((y - y0 + 1) * ew + (x - x0 + 1));
+    const unsigned e = unsigned((y - y0 + H) * ew + (x - x0 + H));
     const unsigned E = unsigned(ew);
     f[0] = C::load(tile, e, W<T>::rest);
     f[1] = C::load(tile + 1 * plane, e - 1, W<T>::axis);
@@ -345,7 +348,7 @@ __device__ __forceinline__ void pull_tile_shifts(const typename Codec<S>::elem *
     f[8] = C::load(tile + 8 * plane, e + E - 1, W<T>::diag);
 }
 
-template <int S>
+template <int S, int H = 1>
 __device__ __forceinline__ void pull_tile(const typename Codec<S>::elem *tile, unsigned plane, int ew,
                                           int x, int y, int x0, int y0, const Geom &g,
                                           typename Codec<S>::real f[9])
@@ -354,12 +357,12 @@ __device__ __forceinline__ void pull_tile(const typename Codec<S>::elem *tile, u
     using T = typename C::real;
     const bool shifts = (g.xper | ((x > 0) & (x < g.nx - 1))) & (g.yper | ((y > 0) & (y < g.ny - 1)));
     if (shifts) {
-        pull_tile_shifts<S>(tile, plane, ew, x, y, x0, y0, f);
+        pull_tile_shifts<S, H>(tile, plane, ew, x, y, x0, y0, f);
     } else {
 #pragma unroll
         for (int a = 0; a < 9; a++) {
             int pa;
-            const unsigned j = tile_source(a, x, y, x0, y0, ew, g, pa);
+            const unsigned j = tile_source<H>(a, x, y, x0, y0, ew, g, pa);
             f[a] = C::load(tile + pa * plane, j, weight<T>(a));
         }
     }
@@ -393,6 +396,15 @@ template <typename T> struct Macro {
 // velocity and force are taken in the algebraically equal forms u = u_s + (j/rho - u_s) k and
 // f = -(j - rho u_s) c with k = 1/(1 + 1/(2 eta)) and c = 1/(eta + 1/2): the literal forms
 // subtract nearly equal numbers (u - u_s is ~eta) and lose about -log10(eta) digits.
+// 1/x: FP64 divides; FP32 takes the hardware reciprocal (1 ulp) and one Newton step, three
+// instructions in place of the ten of a correctly rounded division (within an ulp of it).
+template <typename T> __device__ __forceinline__ T reciprocal(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float reciprocal<float>(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
+
 template <typename T>
 __device__ __forceinline__ Macro<T> moments(const T h[9], bool solid, T usx, T usy, T k_relax, T c_pen)
 {
@@ -401,7 +413,7 @@ __device__ __forceinline__ Macro<T> moments(const T h[9], bool solid, T usx, T u
     T jx = (h[1] - h[3]) + ((h[5] - h[7]) + (h[8] - h[6]));
     T jy = (h[2] - h[4]) + ((h[5] - h[7]) + (h[6] - h[8]));
     T rho = T(1) + drho;
-    T inv_rho = T(1) / rho;
+    T inv_rho = reciprocal(rho);
     m.drho = drho;
     m.rho = rho;
     if (solid) {
@@ -598,6 +610,47 @@ __device__ __forceinline__ void store_node(typename Codec<S>::elem *__restrict__
             else C::store(dst + k * plane, i, f[k], weight<T>(k));
         }
     }
+}
+
+// A buffer resource over `bytes` bytes from p (raw, unformatted dwords): buffer stores through it
+// take the per-lane byte offset in a vector register and a wave-uniform offset (a plane's start)
+// in a scalar one, so they need no 64-bit address arithmetic per lane.  Accesses beyond `bytes`
+// are dropped by the hardware.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_over(void *p, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(p, 0, int(bytes), 0x00020000);   // data format: 32 bit
+}
+
+// pull_interior for 4-byte storage through a buffer resource over the planes (buffer_over): every
+// load takes the node's byte offset 4 i in the same vector register, and the plane's start plus
+// the direction's shift, (a plane + shift) * 4, in a scalar one, so the nine loads need no vector
+// address arithmetic.  Same values as pull_interior.
+template <int S>
+__device__ __forceinline__ void pull_interior_buf(__amdgpu_buffer_rsrc_t r, unsigned plane, unsigned pitch,
+                                                  unsigned i, typename Codec<S>::real f[9])
+{
+    static_assert(sizeof(typename Codec<S>::elem) == 4, "binary32 storage");
+    using T = typename Codec<S>::real;
+    const int v = int(i * 4u);
+    const int P = int(pitch);
+    const int shift[9] = {0, -1, -P, 1, P, -P - 1, -P + 1, P + 1, P - 1};
+#pragma unroll
+    for (int a = 0; a < 9; a++)
+        f[a] = T(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                   r, v, int((unsigned(a) * plane + unsigned(shift[a])) * 4u), 0)));
+}
+
+// store_node for 4-byte storage without stochastic rounding through a buffer resource over the
+// planes (buffer_over): plane k of node i at byte (k plane + i) * 4, the same values and rounding.
+template <int S, bool NT>
+__device__ __forceinline__ void store_node_buf(__amdgpu_buffer_rsrc_t r, unsigned plane, unsigned i,
+                                               const typename Codec<S>::real f[9])
+{
+    static_assert(sizeof(typename Codec<S>::elem) == 4 && !Codec<S>::stochastic, "binary32 storage");
+#pragma unroll
+    for (int k = 0; k < 9; k++)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(float(f[k])), r, int(i * 4u),
+                                              int(unsigned(k) * plane * 4u), NT ? 2 : 0);   // 2: nt
 }
 
 // The whole step at node (x, y): pull, edges, moments and penalization, collision, store.

@@ -104,7 +104,9 @@ struct vplbm_sim_s {
     BodyParams *d_params = nullptr;
     BodyState *d_state = nullptr;
     uint8_t *mask_alt = nullptr;         // moving bodies: mask and body states of the first step of
-    BodyState *d_state_alt = nullptr;    //   a two-step launch (mask / d_state take the second)
+    BodyState *d_state_alt = nullptr;    //   a two- or three-step launch (mask / d_state take the last)
+    uint8_t *mask_alt2 = nullptr;        //   and of the second step of a three-step launch
+    BodyState *d_state_alt2 = nullptr;
     BodyParams h_params[kMaxBodies];
     int nbodies = 0;
     bool device_mask = false;
@@ -126,6 +128,7 @@ struct vplbm_sim_s {
     int graph_flip[2] = {0, 0};          // 1: a replay moves the state to the other buffer
     int graph_k = 0;
     bool two_step = true;                // two steps per launch where the case allows it
+    bool three_step = true;              // three where the kernel exists for the case
     int64_t steps = 0;
     bool unstable = false;
     NodeParams params{};
@@ -164,6 +167,8 @@ StepArgs step_args(vplbm_sim s, int src, int t_off)
     a.bodies = s->d_state;
     a.mask2 = s->mask;
     a.bodies2 = s->d_state;
+    a.mask3 = s->mask;
+    a.bodies3 = s->d_state;
     a.ring = s->ring;
     a.acc = s->acc;
     a.status = s->status;
@@ -233,17 +238,43 @@ bool two_step_ok(vplbm_sim s)
     return s->two_step && (!s->moving || s->mask_alt);
 }
 
-// Enqueue n steps starting from the state in buf[first_src]: pairs of steps in two-step launches
-// (unless VPLBM_TWO_STEP=0 turned them off), one step per launch for an odd last step.  Every
+// Three steps per launch: binary32 storage without a convective outlet, planes below 4 GB (the
+// kernel stores through a 32-bit buffer resource); moving bodies take masks of their own for the
+// first two steps.
+bool three_step_ok(vplbm_sim s)
+{
+    return s->three_step && two_step_ok(s) && step3_supported(s->storage) && !s->outlet[0] &&
+           s->buf_bytes <= 0xFFFFFFFFu && (!s->moving || s->mask_alt2);
+}
+
+// Enqueue n steps starting from the state in buf[first_src]: triples of steps in three-step
+// launches where the case allows them (unless VPLBM_THREE_STEP=0 turned them off), else pairs in
+// two-step launches (unless VPLBM_TWO_STEP=0), and what remains one or two at a time.  Every
 // launch moves the state to the other buffer; *flip is the parity of the number of launches.
 hipError_t enqueue_steps(vplbm_sim s, int first_src, int n, hipStream_t st, int *flip)
 {
     const bool two = two_step_ok(s);
+    const bool three = three_step_ok(s);
     int src = first_src;
     int j = 0;
     while (j < n) {
         hipError_t e;
-        if (two && n - j >= 2) {
+        if (three && n - j >= 3) {
+            StepArgs a = step_args(s, src, j);
+            if (s->moving) {
+                // steps one and two on the other masks, the third on the simulation's own
+                uint8_t *m[3] = {s->mask_alt, s->mask_alt2, s->mask};
+                BodyState *b[3] = {s->d_state_alt, s->d_state_alt2, s->d_state};
+                e = place_bodies_n(s, j, 3, st, m, b);
+                if (e != hipSuccess) return e;
+                a.mask = s->mask_alt;
+                a.bodies = s->d_state_alt;
+                a.mask2 = s->mask_alt2;
+                a.bodies2 = s->d_state_alt2;
+            }
+            e = launch_step3(s->storage, a, st);
+            j += 3;
+        } else if (two && n - j >= 2) {
             StepArgs a = step_args(s, src, j);
             if (s->moving) {
                 // the first step on the other mask, the second on the simulation's own: after
@@ -311,7 +342,8 @@ void release(vplbm_sim s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (int p = 0; p < 2; p++)
         if (s->graph[p]) (void)hipGraphExecDestroy(s->graph[p]);
-    void *ptrs[] = {s->buf[0], s->buf[1], s->mask, s->mask_alt, s->d_params, s->d_state, s->d_state_alt, s->ring, s->acc,
+    void *ptrs[] = {s->buf[0], s->buf[1], s->mask, s->mask_alt, s->mask_alt2, s->d_params, s->d_state,
+                    s->d_state_alt, s->d_state_alt2, s->ring, s->acc,
                     s->status, s->t_dev, s->staging, s->outlet[0], s->outlet[1], s->snap, s->rpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -450,12 +482,14 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     s->nt_store = 2 * s->buf_bytes > ((size_t)192 << 20) ? 1 : 0;
     if (const char *e = getenv("VPLBM_NT_STORE")) s->nt_store = atoi(e) ? 1 : 0;
     if (const char *e = getenv("VPLBM_TWO_STEP")) s->two_step = atoi(e) != 0;   // 0: one step per launch
+    if (const char *e = getenv("VPLBM_THREE_STEP")) s->three_step = atoi(e) != 0; // 0: at most two
     struct { void **p; size_t n; } allocs[] = {
         {&s->buf[0], s->buf_bytes}, {&s->buf[1], s->buf_bytes},
         {(void **)&s->mask, (size_t)g.pitch * g.ny},
         {(void **)&s->d_params, sizeof(BodyParams) * kMaxBodies},
         {(void **)&s->d_state, sizeof(BodyState) * kMaxBodies},
         {(void **)&s->d_state_alt, sizeof(BodyState) * kMaxBodies},
+        {(void **)&s->d_state_alt2, sizeof(BodyState) * kMaxBodies},
         {(void **)&s->ring, sizeof(double) * kRingWidth * s->ring_len},
         {(void **)&s->acc, sizeof(double) * kAccSets * kSub * kRingWidth},
         {(void **)&s->status, sizeof(unsigned) * 4},
@@ -475,6 +509,7 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     hipError_t e = hipMemsetAsync(s->mask, 0, (size_t)g.pitch * g.ny, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_state, 0, sizeof(BodyState) * kMaxBodies, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_state_alt, 0, sizeof(BodyState) * kMaxBodies, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_state_alt2, 0, sizeof(BodyState) * kMaxBodies, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_params, 0, sizeof(BodyParams) * kMaxBodies, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->ring, 0, sizeof(double) * kRingWidth * s->ring_len, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->acc, 0, sizeof(double) * kAccSets * kSub * kRingWidth, s->stream);
@@ -493,8 +528,9 @@ int vplbm_create(const vplbm_config *cfg, vplbm_sim *out)
     track(s, true);
     *out = s;
     host_log("create %p: %dx%d storage %d collision %d, tiles %dx%d x %d rows, %d planes of %d elements, "
-        "non-temporal stores %d, two steps per launch %d", (void *)s, g.nx, g.ny, s->storage, cfg->collision,
-        1 << s->ts.bx_log2, s->ts.by, s->ts.rows, 9, g.plane, s->nt_store, two_step_ok(s) ? 1 : 0);
+        "non-temporal stores %d, steps per launch %d", (void *)s, g.nx, g.ny, s->storage, cfg->collision,
+        1 << s->ts.bx_log2, s->ts.by, s->ts.rows, 9, g.plane, s->nt_store,
+        three_step_ok(s) ? 3 : two_step_ok(s) ? 2 : 1);
     return VPLBM_OK;
 }
 
@@ -554,11 +590,19 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
             }
         }
     }
-    // Moving bodies: the first step of a two-step launch takes a mask of its own.
+    // Moving bodies: the first step of a two-step launch takes a mask of its own, and so do the
+    // first two of a three-step launch.
     if (moving && !s->mask_alt && hipMalloc(&s->mask_alt, (size_t)g.pitch * g.ny) != hipSuccess) {
         (void)hipGetLastError();
         s->mask_alt = nullptr;
         return fail(VPLBM_ENOMEM, "cannot allocate the second mask (%zu bytes)", (size_t)g.pitch * g.ny);
+    }
+    const bool third = moving && s->three_step && step3_supported(s->storage) && !s->outlet[0] &&
+                       s->buf_bytes <= 0xFFFFFFFFu;
+    if (third && !s->mask_alt2 && hipMalloc(&s->mask_alt2, (size_t)g.pitch * g.ny) != hipSuccess) {
+        (void)hipGetLastError();
+        s->mask_alt2 = nullptr;
+        return fail(VPLBM_ENOMEM, "cannot allocate the third mask (%zu bytes)", (size_t)g.pitch * g.ny);
     }
     s->nbodies = nbodies;
     s->moving = moving;
@@ -571,12 +615,15 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
         HIP_TRY(launch_mask(s->mask, g, s->d_params, s->d_state, nbodies, 0, 0, g.nx, g.ny, s->stream));
     }
     if (moving) {
-        // The other mask: the whole lattice now; each two-step launch then rebuilds its swept
-        // boxes at the first step's time, and those of the simulation's own at the second's.
+        // The other masks: the whole lattice now; each launch of several steps then rebuilds
+        // their swept boxes at the times of its first steps, and those of the simulation's own
+        // at its last step's.
         HIP_TRY(launch_mask(s->mask_alt, g, s->d_params, s->d_state, nbodies, 0, 0, g.nx, g.ny, s->stream));
+        if (s->mask_alt2)
+            HIP_TRY(launch_mask(s->mask_alt2, g, s->d_params, s->d_state, nbodies, 0, 0, g.nx, g.ny, s->stream));
     }
-    host_log("set_mask %p: %d bodies, moving %d, two steps per launch %d", (void *)s, nbodies,
-             moving ? 1 : 0, two_step_ok(s) ? 1 : 0);
+    host_log("set_mask %p: %d bodies, moving %d, steps per launch %d", (void *)s, nbodies,
+             moving ? 1 : 0, three_step_ok(s) ? 3 : two_step_ok(s) ? 2 : 1);
     if (s->steps == 0) {
         HIP_TRY(launch_init(s->storage, step_args(s, s->cur ^ 1, 0), nullptr, nullptr, nullptr, s->cfg.rho0, s->cfg.ux0, s->cfg.uy0, s->stream));
         HIP_TRY(reset_outlet(s));
@@ -785,7 +832,7 @@ int vplbm_residual(vplbm_sim s, double *residual)
 int vplbm_steps_per_launch(vplbm_sim s, int32_t *steps)
 {
     if (!valid(s) || !steps) return fail(VPLBM_EINVAL, "invalid handle or NULL output");
-    *steps = two_step_ok(s) ? 2 : 1;
+    *steps = three_step_ok(s) ? 3 : two_step_ok(s) ? 2 : 1;
     return VPLBM_OK;
 }
 
