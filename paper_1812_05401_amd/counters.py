@@ -12,8 +12,9 @@ the digest of the kernel sources it was measured on.
     python3 -m paper_1812_05401_amd.counters trace DIR
 
 Each DIR is a `rocprofv3 --pmc ... -d DIR` output folder of one run (its .db files are found
-below it).  The step kernels of a run are `vplbm::step2_kernel` (two lattice updates per launch)
-and `vplbm::step_kernel` (one); per kernel the median over its dispatches is taken.
+below it).  The step kernels of a run are `vplbm::step3_kernel` (three lattice updates per
+launch), `vplbm::step2_kernel` (two) and `vplbm::step_kernel` (one); per kernel the median over
+its dispatches is taken.
 """
 import argparse
 import glob
@@ -80,7 +81,9 @@ def step_kernels(vals, counter):
     for (k, c), vs in vals.items():
         if c != counter:
             continue
-        if k.startswith("vplbm::step2_kernel"):
+        if k.startswith("vplbm::step3_kernel"):
+            spl = 3
+        elif k.startswith("vplbm::step2_kernel"):
             spl = 2
         elif k.startswith("vplbm::step_kernel"):
             spl = 1
@@ -138,7 +141,8 @@ def traffic(specs, copy_dirs, copy_bytes, profile="profiles/step_kernel_hbm_traf
             kname, n, fkib = fk[spl]
             wkib = wk[spl][2]
             rd, wr = fkib * 1024 * fs, wkib * 1024 * ws
-            alg = (bytes_per_update(storage) + (1 if spl == 2 and moving(case) else 0)) * case.nodes
+            # moving bodies: a launch of several steps reads the mask of each of its steps
+            alg = (bytes_per_update(storage) + (spl - 1 if moving(case) else 0)) * case.nodes
             ent = {"kernel": kname, "dispatches": n, "lattice_updates_per_launch": spl,
                    "fetch_kib_raw": fkib, "write_kib_raw": wkib,
                    "fetch_scale": round(fs, 4), "write_scale": round(ws, 4),
@@ -226,7 +230,7 @@ def trace(folder):
     segs = []
     for name, _, dur, grid, *_ in disp:
         k = short(name)
-        if not k.startswith(("vplbm::step2_kernel", "vplbm::step_kernel")):
+        if not k.startswith(("vplbm::step3_kernel", "vplbm::step2_kernel", "vplbm::step_kernel")):
             continue
         if segs and segs[-1][0] == (k, grid):
             segs[-1][1].append(dur / 1e3)

@@ -291,10 +291,13 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
 // position across a periodic edge holds the wrapped node; one beyond a non-periodic edge or a
 // ragged tile is skipped (no later pull reads it).  The phases take the masks and body states of
 // their own steps (a.mask, a.mask2, a.mask3).  There is no convective outlet here: the host uses
-// the two-step kernel for it.  Tiles: 128 x 6 for binary32 (46 KB of LDS, three workgroups per
-// CU; the phases cover 1320, 1040 and 768 nodes).  Inner tiles load and the last phase stores
-// through buffer resources (pull_interior_buf, store_node_buf), which keep the plane offsets out
-// of the vector ALUs.
+// the two-step kernel for it.  Tiles: 64 x 14 for binary32 (46 KB of LDS, three workgroups per
+// CU; the phases cover 1224, 1056 and 896 nodes, 1.18 computed per update).  Measured at
+// 8192 x 2048: 111 us per step, against 113 for 64 x 12, 116 for 64 x 16, 118 for 32 x 24, 123 for
+// 128 x 6 and 64 x 10, 127 for 128 x 10, 137 for 128 x 8 (two workgroups per CU) and 151 for
+// 256 x 4: the VALUs bound this kernel, and taller tiles recompute less halo.  Inner tiles load and
+// the last phase stores through buffer resources (pull_interior_buf, store_node_buf), which keep
+// the plane offsets out of the vector ALUs.
 template <int S, int TW, int TH, bool NT>
 __global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
 {
@@ -541,7 +544,7 @@ bool step3_supported(int storage) { return storage == kF32; }
 
 hipError_t launch_step3(int storage, const StepArgs &a, hipStream_t st)
 {
-    constexpr int TW = 128, TH = 6;
+    constexpr int TW = 64, TH = 14;
     if (storage != kF32 || a.outlet.prev) return hipErrorInvalidValue;
     const dim3 grid(((a.g.nx + TW - 1) / TW) * ((a.g.ny + TH - 1) / TH)), block(kBlock2);
     if (a.nt_store) step3_kernel<kF32, TW, TH, true><<<grid, block, 0, st>>>(a);

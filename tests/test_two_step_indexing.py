@@ -173,7 +173,7 @@ def locate(ux, uy, h, nx, ny, xper, yper):
     return x, y
 
 
-def check_lattice3(nx, ny, xper, yper, tw=128, th=6):
+def check_lattice3(nx, ny, xper, yper, tw=64, th=14):
     """step3_kernel's three phases on every tile: phase 2 reads, at every pull, a slot phase 1 wrote
     with the node edge_source names (and writes its result back over its own node's slot), phase 3
     reads slots phase 2 wrote with the nodes edge_source names, the interior fast path holds only
@@ -220,11 +220,12 @@ def check_lattice3(nx, ny, xper, yper, tw=128, th=6):
     assert sorted(owned) == sorted((x, y) for x in range(nx) for y in range(ny))
 
 
+@pytest.mark.parametrize("tw,th", [(64, 14), (128, 6)])
 @pytest.mark.parametrize("xper,yper", [(0, 0), (0, 1), (1, 0), (1, 1)])
-def test_three_step_phases_read_what_the_previous_wrote(xper, yper):
-    for nx, ny in [(3, 3), (4, 5), (5, 7), (128, 6), (130, 9), (257, 13), (200, 17), (131, 1 + 12),
-                   (390, 30)]:
-        check_lattice3(nx, ny, xper, yper)
+def test_three_step_phases_read_what_the_previous_wrote(xper, yper, tw, th):
+    for nx, ny in [(3, 3), (4, 5), (5, 7), (64, 14), (128, 6), (130, 9), (257, 13), (200, 17),
+                   (131, 1 + 12), (390, 30), (135, 45)]:
+        check_lattice3(nx, ny, xper, yper, tw, th)
 
 
 def test_three_step_reduction_sets_are_distinct_and_folded_before_cleared():
