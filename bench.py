@@ -44,13 +44,13 @@ from paper_1812_05401_amd.counters import source_digest  # noqa: E402  (the coun
 def pattern_ceilings(nx, ny, launches=64):
     """The step kernels' access patterns with a trivial per-node update (libvplbm_probes.so) on an
     nx x ny FP32 lattice: microseconds per launch with 1, 2 and 3 updates per launch (the one-step
-    kernel's 128 x 2 workgroups, the two-step kernel's 128 x 8 tiles, 128 x 6 tiles for three), the
-    best of three timings.  A probe needs the lattice to be a whole number of tiles: otherwise it
+    kernel's 128 x 2 workgroups, the two-step kernel's 128 x 8 tiles, the three-step kernel's
+    64 x 14 tiles), the best of three timings.  A probe needs the lattice to be a whole number of tiles: otherwise it
     runs on the largest such lattice inside and its time is scaled by the node count.  The FP32 FMA issue rate of
     independent chains comes with it."""
     from paper_1812_05401_amd import probes as P
     out = {"lattice": f"{nx}x{ny}", "storage": "f32", "bytes_per_node_per_launch": 73}
-    for spl, tile in ((1, (128, 2)), (2, (128, 8)), (3, (128, 6))):
+    for spl, tile in ((1, (128, 2)), (2, (128, 8)), (3, (64, 14))):
         nxt, nyt = nx - nx % tile[0], ny - ny % tile[1]
         us = min(P.pattern_us(nxt, nyt, spl, tile, launches) for _ in range(3)) * (nx * ny) / (nxt * nyt)
         out[f"steps_per_launch_{spl}"] = {"tile": list(tile), "us_per_launch": round(us, 2),

@@ -30,8 +30,8 @@ extern "C" {
         steps_per_launch - 1 nodes from global memory into an LDS tile; with 3, a middle phase
         updates the tile and a one-node halo in place in LDS; the last phase pulls from LDS and
         stores the tile with non-temporal stores (the two-step kernel's pattern and its
-        three-step extension).  Tiles: 128 x 8, 64 x 8, 128 x 16 for 2; 128 x 8, 128 x 6, 64 x 8
-        for 3.  nx must be a multiple of tile_w and ny of tile_h.
+        three-step kernel's).  Tiles: 128 x 8, 64 x 8, 128 x 16 for 2; 64 x 14, 128 x 8, 128 x 6,
+        64 x 8 for 3.  nx must be a multiple of tile_w and ny of tile_h.
    Each node's update halves its nine values and adds a multiple of its mask byte, so every byte
    loaded is used.  Workgroups map to tiles as in the step kernels (each XCD takes a contiguous
    range).  `launches` timed launches follow launches / 8 + 1 untimed ones; *us_per_launch is

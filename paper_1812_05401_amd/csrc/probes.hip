@@ -240,6 +240,7 @@ int vplbm_probe_pattern(int32_t nx, int32_t ny, int32_t steps_per_launch, int32_
         case 312808: fn = launch_tile<128, 8, 3>; break;
         case 312806: fn = launch_tile<128, 6, 3>; break;
         case 306408: fn = launch_tile<64, 8, 3>; break;
+        case 306414: fn = launch_tile<64, 14, 3>; break;
         default:
             return fail(-1, "no probe for " + std::to_string(steps_per_launch) + " steps per launch on " +
                                 std::to_string(tile_w) + " x " + std::to_string(tile_h) + " tiles");
