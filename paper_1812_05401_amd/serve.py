@@ -67,8 +67,12 @@ def run_pool(requests, budget_bytes, max_slots=128, steps_per_launch=64, stream=
     return _summary(order, done_at, wall, max_running=max_running), results
 
 
-def run_fifo(requests, stream=None):
-    """Baseline: one simulation at a time through the single-simulation API, in arrival order."""
+def run_fifo(requests, stream=None, reduce=True):
+    """Baseline: one simulation at a time through the single-simulation API, in arrival order.
+    With reduce (the default) each simulation's final mass and body forces come back as the
+    pool's results do; the single-simulation API reduces every step for that (the pool only the
+    final one), a few percent of its step time.  reduce=False skips the reductions and returns no
+    observables."""
     order = sorted(requests, key=lambda r: r.arrival)
     t0 = time.perf_counter()
     done_at = {}
@@ -76,7 +80,7 @@ def run_fifo(requests, stream=None):
         wait = req.arrival - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
-        sim = B.Simulation(req.case, stream=stream, reduce=False)
+        sim = B.Simulation(req.case, stream=stream, reduce=reduce)
         sim.step(req.case.steps)
         sim.observables()
         sim.close()
