@@ -199,11 +199,13 @@ int vplbm_momentum_exchange_noalloc(vplbm_sim s, double *out);
 int vplbm_steps_done(vplbm_sim s, int64_t *steps);
 int vplbm_stream(vplbm_sim s, void **stream);
 
-/* Lattice updates per kernel launch for this simulation: 2 when pairs of steps run in one launch
-   with the intermediate step kept on chip (moving bodies get a second mask for the first step of
-   each pair), 1 when the environment variable VPLBM_TWO_STEP=0 was set at create.  An odd last
-   step of a call always takes a launch of its own.  Either way the results are bitwise the same
-   (the update of Section 2 per node and step).  EINVAL: bad handle or NULL out. */
+/* Lattice updates per kernel launch for this simulation: 3 for binary32 storage without a
+   convective outlet (the two intermediate steps kept on chip, 64 x 14 tiles), 2 for the other cases
+   (pairs of steps, the intermediate one kept on chip), 1 when the environment variable
+   VPLBM_TWO_STEP=0 was set at create; VPLBM_THREE_STEP=0 at create caps it at 2.  Moving bodies
+   get a mask of their own for each intermediate step.  What remains of a call after its full
+   launches takes launches of one or two steps.  Every launch shape gives bitwise the same
+   populations (the update of Section 2 per node and step).  EINVAL: bad handle or NULL out. */
 int vplbm_steps_per_launch(vplbm_sim s, int32_t *steps);
 
 /* Algorithmic HBM bytes of one lattice update for a storage format: 9 population loads,
@@ -213,7 +215,8 @@ int vplbm_bytes_per_update(int32_t storage, int64_t *bytes);
 /* ---- serving pool -----------------------------------------------------------------------
  * Many independent simulations resident on one GPU at once, advanced together: every call to
  * vplbm_pool_advance replays one captured HIP graph of `steps_per_launch` steps of a batched
- * step kernel (two steps per launch with the first kept on chip, an odd one last) with one
+ * step kernel (three steps per launch for binary32 storage and two for the other formats, the
+ * intermediate steps kept on chip, what remains of a replay last) with one
  * workgroup per tile of a device table spanning all resident simulations (each simulation's
  * per-node arithmetic is the single-simulation step's), then
  * retires the finished ones and admits queued requests, first come first served, while the

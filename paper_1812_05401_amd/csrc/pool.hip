@@ -2,10 +2,12 @@
 // replayed from a captured HIP graph (see the pool section of include/vplbm.h).
 //
 // Device side.  A descriptor per slot (buffers, geometry, parameters, admission step, target) and
-// a table of 64 x 8 tiles covering every resident simulation.  One workgroup per tile and two
-// steps per launch, the first kept in LDS as in the single-simulation two-step kernel; each tile
-// runs the same per-node update as the single-simulation step, so a simulation's fields do not
-// depend on its co-residents or on the launch shape.  All resident simulations advance together, so a simulation's
+// a table of tiles covering every resident simulation.  One workgroup per tile.  Binary32
+// simulations take three steps per launch on 64 x 14 tiles, the first two kept in LDS as in the
+// single-simulation three-step kernel; the other formats two steps per launch on 64 x 8 tiles, the
+// first kept in LDS as in the two-step kernel.  Each tile runs the same per-node update as the
+// single-simulation step, so a simulation's fields do not depend on its co-residents or on the
+// launch shape.  All resident simulations advance together, so a simulation's
 // steps done are the pool's step counter (on the device) minus its admission step: no per-step
 // bookkeeping launch is needed.  On a simulation's final step each tile writes its FP64 partial
 // sums (mass, body forces) to its own slot, summed in a fixed order inside the tile; at
@@ -40,6 +42,9 @@ namespace vplbm {
 
 constexpr int kPoolTileW = 64, kPoolTileH = 8;   // 512 nodes: one per thread of kBlock2
 constexpr int kPoolEW = kPoolTileW + 2, kPoolEN = kPoolEW * (kPoolTileH + 2);
+// binary32: three steps per launch on 64 x 14 tiles, an LDS tile with a two-node halo
+constexpr int kPool3H = 14;
+constexpr int kPool3EW = kPoolTileW + 4, kPool3EN = kPool3EW * (kPool3H + 4);
 constexpr int kPoolMaxSlots = 1024;
 static_assert(kPoolTileW * kPoolTileH == kBlock2, "one node per thread in the second step");
 
@@ -52,6 +57,8 @@ struct PoolSim {
     NodeParams p;
     int storage;
     int ntx, ntiles;
+    int th;                  // tile height (the tile width is kPoolTileW)
+    int spk;                 // steps per kernel launch: 3 for binary32, else 2
     int active;
     int spl;                 // steps per graph replay (the pool's steps_per_launch)
     long long t0, target;    // pool step at admission; steps to run
@@ -70,12 +77,12 @@ struct TileRef {
 };
 
 // Buffer holding a simulation's state after `done` steps.  Each graph replay of spl steps runs
-// ceil(spl / 2) launches from the replay's start, pairs of steps and an odd one last; a simulation
-// is admitted at a replay boundary, and a launch moves its state to the other buffer whether it
-// takes one step or two (one when the simulation has a single step left).
-__host__ __device__ inline int pool_buf(long long done, int spl)
+// ceil(spl / spk) launches of the simulation's kernel from the replay's start, spk steps each and
+// what remains last; a simulation is admitted at a replay boundary, and a launch moves its state
+// to the other buffer however many steps it takes (fewer when the simulation has fewer left).
+__host__ __device__ inline int pool_buf(long long done, int spl, int spk)
 {
-    const long long launches = (done / spl) * ((spl + 1) / 2) + ((done % spl) + 1) / 2;
+    const long long launches = (done / spl) * ((spl + spk - 1) / spk) + ((done % spl) + spk - 1) / spk;
     return (int)(launches & 1);
 }
 
@@ -121,7 +128,7 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
     using T = typename C::real;
     using E = typename C::elem;
     const Geom &g = d.g;
-    const int b = pool_buf(done, d.spl);
+    const int b = pool_buf(done, d.spl, d.spk);
     const E *__restrict__ src = static_cast<const E *>(d.buf[b]);
     E *__restrict__ dst = static_cast<E *>(d.buf[b ^ 1]);
     const Outlet none{nullptr, nullptr, 0.0};
@@ -183,25 +190,194 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
     if (done + nsteps == d.target) pool_tile_partials<wave_sum_dpp<T>()>(d, tile, rho, fx, fy, id, part);
 }
 
-// Storage formats by arithmetic: class 1 computes in FP64 (F64, F32D), class 0 in FP32 with at
-// most 4-byte storage.  Each class has a kernel of its own, so the FP32 formats are not held to
-// the FP64 path's registers and LDS: measured 4 waves per SIMD with one kernel for all.
-__host__ __device__ inline int pool_class(int storage)
+// The lattice node at unwrapped position (ux, uy) of a tile, h or fewer nodes outside it: live
+// unless beyond a non-periodic edge or more than h beyond the lattice (a ragged tile); a position
+// across a periodic edge is the wrapped node.
+__device__ __forceinline__ bool pool_locate(const Geom &g, int ux, int uy, int h, int &x, int &y)
 {
-    return storage == kF64 || storage == kF32D ? 1 : 0;
+    x = ux;
+    y = uy;
+    if (x < 0 || x >= g.nx) {
+        if (g.xper && x >= -h && x < g.nx + h) x += x < 0 ? g.nx : -g.nx;
+        else return false;
+    }
+    if (y < 0 || y >= g.ny) {
+        if (g.yper && y >= -h && y < g.ny + h) y += y < 0 ? g.ny : -g.ny;
+        else return false;
+    }
+    return true;
 }
 
-// Steps t_off and t_off + 1 (nsteps = 2) or step t_off alone (nsteps = 1) of the graph replay, for
-// every resident simulation of class CLASS: workgroup w (< *ntiles) updates one tile (tiles of
-// the other class return at once); a simulation with a single step left takes it alone.
+// First phase of a multi-step launch on a 64 x kPool3H tile: step `step` on the tile and a halo
+// of H nodes, from the planes in global memory into the LDS tile, whose slots are laid out with a
+// two-node halo (kPool3EW per row) whatever H is.  Returns whether an own node went bad.
+template <int S, int H>
+__device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typename Codec<S>::elem *src,
+                                                 typename Codec<S>::elem *mid, int x0, int y0,
+                                                 unsigned step)
+{
+    using T = typename Codec<S>::real;
+    constexpr int W1 = kPoolTileW + 2 * H, N1 = W1 * (kPool3H + 2 * H);
+    const Geom &g = d.g;
+    const Outlet none{nullptr, nullptr, 0.0};
+    bool bad = false;
+    for (int e = threadIdx.x; e < N1; e += kBlock2) {
+        const int ux = x0 + e % W1 - H, uy = y0 + e / W1 - H;
+        int x, y;
+        if (!pool_locate(g, ux, uy, H, x, y)) continue;
+        T f[9];
+        int id;
+        pull<S>(src, x, y, g, none, f);
+        const auto m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
+        store_node<S>(mid, kPool3EN, unsigned((uy - y0 + 2) * kPool3EW + (ux - x0 + 2)), f,
+                      unsigned(y * g.pitch + x), step);
+        const bool own = (ux >= x0) & (ux < x0 + kPoolTileW) & (uy >= y0) & (uy < y0 + kPool3H) &
+                         (ux < g.nx) & (uy < g.ny);
+        const double r1 = 1.0 + double(m.drho);
+        bad |= own && !(r1 > 0.0 && r1 < 1e30);
+    }
+    return bad;
+}
+
+// One 64 x kPool3H tile of a binary32 simulation for k (1 to 3) steps from `done`, as the
+// single-simulation kernels compute them: for k = 3 step done on the tile and a two-node halo into
+// LDS, step done + 1 on the tile and a one-node halo in place (its results held in registers
+// until every pull is made), step done + 2 of the tile to global memory; for k = 2 the first
+// phase with a one-node halo and the last; for k = 1 the last alone, from global memory.  On the
+// simulation's final step the tile's FP64 sums go to its slot of the partials (per-wave rows
+// added in order, rows in order).
+template <int S>
+__device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long done, int k,
+                                           unsigned char *lds, double (*part)[kRingWidth])
+{
+    using C = Codec<S>;
+    using T = typename C::real;
+    using E = typename C::elem;
+    constexpr int TW = kPoolTileW, TH = kPool3H, EW = kPool3EW, EN = kPool3EN;
+    constexpr bool DPP = wave_sum_dpp<T>();
+    const Geom &g = d.g;
+    const int b = pool_buf(done, d.spl, d.spk);
+    const E *__restrict__ src = static_cast<const E *>(d.buf[b]);
+    E *__restrict__ dst = static_cast<E *>(d.buf[b ^ 1]);
+    const Outlet none{nullptr, nullptr, 0.0};
+    const int x0 = (tile % d.ntx) * TW, y0 = (tile / d.ntx) * TH;
+    E *mid = reinterpret_cast<E *>(lds);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool final_step = done + k == d.target;             // uniform over the workgroup
+    if (final_step && lane < kRingWidth) part[wave][lane] = 0.0;
+    bool bad = false;
+    if (k == 3) {
+        bad |= pool_first_phase<S, 2>(d, src, mid, x0, y0, (unsigned)done);
+        __syncthreads();
+        constexpr int MW = TW + 2, MN = MW * (TH + 2), R2 = (MN + kBlock2 - 1) / kBlock2;
+        T res[R2][9];
+        int slot[R2];
+        unsigned node[R2];
+#pragma unroll
+        for (int it = 0; it < R2; it++) {
+            const int j = threadIdx.x + it * kBlock2;
+            const int ux = x0 + j % MW - 1, uy = y0 + j / MW - 1;
+            int x, y;
+            slot[it] = -1;
+            node[it] = 0;
+            if (j < MN && pool_locate(g, ux, uy, 1, x, y)) {
+                int id;
+                pull_tile<S, 2>(mid, EN, EW, ux, uy, x0, y0, g, res[it]);
+                const auto m = relax_node(res[it], d.mask, d.bodies, g, d.p, x, y, id);
+                slot[it] = (j / MW + 1) * EW + j % MW + 1;
+                node[it] = unsigned(y * g.pitch + x);
+                const bool own = (ux >= x0) & (ux < x0 + TW) & (uy >= y0) & (uy < y0 + TH) &
+                                 (ux < g.nx) & (uy < g.ny);
+                const double r1 = 1.0 + double(m.drho);
+                bad |= own && !(r1 > 0.0 && r1 < 1e30);
+            }
+        }
+        __syncthreads();                          // every middle-phase pull has read step done
+#pragma unroll
+        for (int it = 0; it < R2; it++)
+            if (slot[it] >= 0) store_node<S>(mid, EN, unsigned(slot[it]), res[it], node[it], (unsigned)(done + 1));
+        __syncthreads();
+    } else if (k == 2) {
+        bad |= pool_first_phase<S, 1>(d, src, mid, x0, y0, (unsigned)done);
+        __syncthreads();
+    }
+    constexpr int R3 = (TW * TH + kBlock2 - 1) / kBlock2;
+#pragma unroll
+    for (int it = 0; it < R3; it++) {
+        const int j = threadIdx.x + it * kBlock2;
+        const int x = x0 + j % TW, y = y0 + j / TW;
+        double rho = 0.0, fx = 0.0, fy = 0.0;
+        int id = 0;
+        if ((j < TW * TH) & (x < g.nx) & (y < g.ny)) {
+            Macro<T> m;
+            if (k == 1) {
+                m = update_node<S>(src, dst, d.mask, d.bodies, g, none, d.p, x, y, id, (unsigned)done);
+            } else {
+                T f[9];
+                pull_tile<S, 2>(mid, EN, EW, x, y, x0, y0, g, f);
+                m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
+                const unsigned i = y * g.pitch + x;
+                store_node<S>(dst, g.plane, i, f, i, (unsigned)(done + k - 1));
+            }
+            rho = 1.0 + double(m.drho);
+            fx = double(m.fx);
+            fy = double(m.fy);
+            bad |= !(rho > 0.0 && rho < 1e30);
+        }
+        if (final_step) {
+            // this round's nodes into the wave's row (lane 0 of the wave adds, in round order)
+            const double mw = wave_sum<DPP>(rho);
+            if (lane == 0) part[wave][0] += mw;
+            unsigned long long solid = __ballot(id != 0);
+            while (solid) {
+                const int lead = __ffsll((unsigned long long)solid) - 1;
+                const int bb = __shfl(id, lead, 64);
+                const bool mine = id == bb;
+                const double sx = wave_sum<DPP>(mine ? -fx : 0.0);
+                const double sy = wave_sum<DPP>(mine ? -fy : 0.0);
+                if (lane == 0) {
+                    part[wave][1 + 2 * (bb - 1)] += sx;
+                    part[wave][2 + 2 * (bb - 1)] += sy;
+                }
+                solid &= ~__ballot(mine);
+            }
+        }
+    }
+    if (__ballot(bad) && lane == 0) atomicOr(const_cast<unsigned *>(&d.status), 1u);
+    if (final_step) {
+        __syncthreads();
+        if (threadIdx.x < kRingWidth) {
+            double v = 0.0;
+            for (int w = 0; w < kBlock2 / 64; w++) v += part[w][threadIdx.x];
+            d.partials[(size_t)tile * kRingWidth + threadIdx.x] = v;
+        }
+    }
+}
+
+// Storage formats by kernel: class 1 computes in FP64 (F64, F32D), class 0 in FP32 with 2-byte
+// storage, both two steps per launch; class 2 is binary32 storage, three steps per launch.  Each
+// class has a kernel of its own, so the FP32 formats are not held to the FP64 path's registers
+// and LDS: measured 4 waves per SIMD with one kernel for all.
+__host__ __device__ inline int pool_class(int storage)
+{
+    return storage == kF64 || storage == kF32D ? 1 : (storage == kF32 ? 2 : 0);
+}
+
+// Tile height and steps per kernel launch of a storage format's class.
+__host__ __device__ inline int pool_tile_h(int storage) { return pool_class(storage) == 2 ? kPool3H : kPoolTileH; }
+__host__ __device__ inline int pool_spk(int storage) { return pool_class(storage) == 2 ? 3 : 2; }
+
+// Steps t_off .. t_off + nsteps - 1 of the graph replay (nsteps up to the class's steps per
+// launch), for every resident simulation of class CLASS: workgroup w (< *ntiles) updates one tile
+// (tiles of the other classes return at once); a simulation with fewer steps left takes those.
 template <int CLASS>
 __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const TileRef *tiles,
                                                             const int *ntiles,
                                                             const long long *t_base, int t_off,
                                                             int nsteps)
 {
-    // the first step's tile in the class's widest storage format
-    __shared__ __align__(16) unsigned char lds[9 * kPoolEN * (CLASS ? 8 : 4)];
+    // the LDS tile in the class's widest storage format
+    __shared__ __align__(16) unsigned char lds[CLASS == 2 ? 9 * kPool3EN * 4 : 9 * kPoolEN * (CLASS ? 8 : 4)];
     __shared__ double part[kBlock2 / 64][kRingWidth];
     const int n = *ntiles;
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
@@ -210,13 +386,14 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     const long long done = *t_base + t_off - d.t0;
     if (!d.active || done < 0 || done >= d.target) return;    // uniform over the workgroup
     if (pool_class(d.storage) != CLASS) return;
-    const int k = d.target - done < nsteps ? 1 : nsteps;
-    if constexpr (CLASS == 1) {
+    const int k = d.target - done < nsteps ? int(d.target - done) : nsteps;
+    if constexpr (CLASS == 2) {
+        pool_tile3<kF32>(d, tr.tile, done, k, lds, part);
+    } else if constexpr (CLASS == 1) {
         if (d.storage == kF64) pool_tile<kF64>(d, tr.tile, done, k, lds, part);
         else pool_tile<kF32D>(d, tr.tile, done, k, lds, part);
     } else {
         switch (d.storage) {
-        case kF32: pool_tile<kF32>(d, tr.tile, done, k, lds, part); break;
         case kF16S: pool_tile<kF16S>(d, tr.tile, done, k, lds, part); break;
         case kF16SR: pool_tile<kF16SR>(d, tr.tile, done, k, lds, part); break;
         case kBF16SR: pool_tile<kBF16SR>(d, tr.tile, done, k, lds, part); break;
@@ -277,19 +454,24 @@ __global__ __launch_bounds__(kBlock2) void pool_residual_kernel(PoolSim *sims, c
     const long long done = *t_base + t_off - d.t0;
     if (!residual_due(d, done)) return;                       // uniform over the workgroup
     const int x = (tr.tile % d.ntx) * kPoolTileW + lane;
-    const int y = (tr.tile / d.ntx) * kPoolTileH + wave;
+    const int y0 = (tr.tile / d.ntx) * d.th;
     double d2 = 0.0, u2 = 0.0;
-    if (x < d.g.nx && y < d.g.ny) {
-        const int parity = pool_buf(done, d.spl);
+    const int parity = pool_buf(done, d.spl, d.spk);
+    for (int r = wave; r < d.th; r += kBlock2 / 64) {          // rows of the tile, in order
+        const int y = y0 + r;
+        if (x >= d.g.nx || y >= d.g.ny) continue;
+        double a2 = 0.0, b2 = 0.0;
         switch (d.storage) {
-        case kF64: pool_residual_node<kF64>(d, parity, x, y, d2, u2); break;
-        case kF32: pool_residual_node<kF32>(d, parity, x, y, d2, u2); break;
-        case kF16S: pool_residual_node<kF16S>(d, parity, x, y, d2, u2); break;
-        case kF32D: pool_residual_node<kF32D>(d, parity, x, y, d2, u2); break;
-        case kF16SR: pool_residual_node<kF16SR>(d, parity, x, y, d2, u2); break;
-        case kBF16SR: pool_residual_node<kBF16SR>(d, parity, x, y, d2, u2); break;
-        default: pool_residual_node<kBF16S>(d, parity, x, y, d2, u2); break;
+        case kF64: pool_residual_node<kF64>(d, parity, x, y, a2, b2); break;
+        case kF32: pool_residual_node<kF32>(d, parity, x, y, a2, b2); break;
+        case kF16S: pool_residual_node<kF16S>(d, parity, x, y, a2, b2); break;
+        case kF32D: pool_residual_node<kF32D>(d, parity, x, y, a2, b2); break;
+        case kF16SR: pool_residual_node<kF16SR>(d, parity, x, y, a2, b2); break;
+        case kBF16SR: pool_residual_node<kBF16SR>(d, parity, x, y, a2, b2); break;
+        default: pool_residual_node<kBF16S>(d, parity, x, y, a2, b2); break;
         }
+        d2 += a2;
+        u2 += b2;
     }
     d2 = wave_sum(d2);
     u2 = wave_sum(u2);
@@ -371,8 +553,9 @@ int pool_geometry(const vplbm_config &c, Geom &g, int &ntx, int &ntiles)
     g.xper = c.bc_xlo == VPLBM_PERIODIC;
     g.yper = c.bc_ylo == VPLBM_PERIODIC;
     g.inlet = c.bc_xlo == VPLBM_VELOCITY;
+    const int th = pool_tile_h(c.storage);
     ntx = (c.nx + kPoolTileW - 1) / kPoolTileW;
-    ntiles = ntx * ((c.ny + kPoolTileH - 1) / kPoolTileH);
+    ntiles = ntx * ((c.ny + th - 1) / th);
     return VPLBM_OK;
 }
 
@@ -494,7 +677,7 @@ int retire(vplbm_pool p, int slot)
         r.ux.resize(n);
         r.uy.resize(n);
         StepArgs a{};
-        a.src = d.buf[pool_buf(done, d.spl)];   // the state after `done` steps
+        a.src = d.buf[pool_buf(done, d.spl, d.spk)];   // the state after `done` steps
         a.mask = d.mask;
         a.bodies = d.bodies;
         a.t_base = p->d_zero;
@@ -570,6 +753,8 @@ int admit(vplbm_pool p, Request &r, int slot)
     d.partials = r.partials;
     d.p = node_params(r.cfg);
     d.storage = r.cfg.storage;
+    d.th = pool_tile_h(d.storage);
+    d.spk = pool_spk(d.storage);
     d.active = 1;
     d.spl = p->cfg.steps_per_launch;
     d.t0 = p->t_host;
@@ -625,9 +810,11 @@ int ensure_pool_graph(vplbm_pool p)
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    // pairs of steps from the replay's start, an odd one last (pool_buf counts launches this way)
-    for (int j = 0; j < p->cfg.steps_per_launch && e == hipSuccess; j += 2) {
-        const int nsteps = p->cfg.steps_per_launch - j >= 2 ? 2 : 1;
+    // Each class's launches from the replay's start: spk steps each (2, or 3 for binary32), what
+    // remains last (pool_buf counts launches this way).  The classes advance the same steps.
+    const int spl = p->cfg.steps_per_launch;
+    for (int j = 0; j < spl && e == hipSuccess; j += 2) {
+        const int nsteps = spl - j >= 2 ? 2 : 1;
         if (classes & 1) {
             pool_step_kernel<0><<<dim3(cap), dim3(kBlock2), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j, nsteps);
             e = hipGetLastError();
@@ -636,6 +823,11 @@ int ensure_pool_graph(vplbm_pool p)
             pool_step_kernel<1><<<dim3(cap), dim3(kBlock2), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j, nsteps);
             e = hipGetLastError();
         }
+    }
+    for (int j = 0; j < spl && e == hipSuccess && (classes & 4); j += 3) {
+        const int nsteps = spl - j >= 3 ? 3 : spl - j;
+        pool_step_kernel<2><<<dim3(cap), dim3(kBlock2), 0, p->cap_stream>>>(p->d_sims, p->d_tiles, p->d_ntiles, p->d_t, j, nsteps);
+        e = hipGetLastError();
     }
     if (e == hipSuccess && checks) {
         const int n = p->cfg.steps_per_launch;

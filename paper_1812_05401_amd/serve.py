@@ -26,7 +26,8 @@ def _percentiles(ttr):
 def run_pool(requests, budget_bytes, max_slots=128, steps_per_launch=64, stream=None,
              keep_fields=False, on_result=None, poll_sleep_s=0.0005,
              max_resident_nodes=DEFAULT_RESIDENT_NODES):
-    """Replay `requests` through a Pool.  Returns summary statistics and per-request results."""
+    """Replay `requests` through a Pool.  Returns summary statistics (with the number of requests
+    that failed: a non-finite or non-positive density) and per-request results."""
     pool = B.Pool(budget_bytes, max_slots=max_slots, steps_per_launch=steps_per_launch,
                   stream=stream)
     if max_resident_nodes:
@@ -38,6 +39,7 @@ def run_pool(requests, budget_bytes, max_slots=128, steps_per_launch=64, stream=
     pending = {}          # pool id -> request
     done_at, results = {}, {}
     max_running = 0
+    failed = 0
     while len(done_at) < n:
         now = time.perf_counter() - t0
         while i < n and order[i].arrival <= now:
@@ -52,6 +54,7 @@ def run_pool(requests, budget_bytes, max_slots=128, steps_per_launch=64, stream=
             if st in (B.DONE, B.FAILED):
                 req = pending.pop(rid)
                 res = pool.result(rid, fields=keep_fields)
+                failed += st == B.FAILED
                 done_at[req.rid] = t_now
                 results[req.rid] = res
                 if on_result:
@@ -64,29 +67,30 @@ def run_pool(requests, budget_bytes, max_slots=128, steps_per_launch=64, stream=
             time.sleep(poll_sleep_s)
     wall = time.perf_counter() - t0
     pool.close()
-    return _summary(order, done_at, wall, max_running=max_running), results
+    return _summary(order, done_at, wall, max_running=max_running, failed=failed), results
 
 
 def run_fifo(requests, stream=None, reduce=True):
     """Baseline: one simulation at a time through the single-simulation API, in arrival order.
     With reduce (the default) each simulation's final mass and body forces come back as the
     pool's results do; the single-simulation API reduces every step for that (the pool only the
-    final one), a few percent of its step time.  reduce=False skips the reductions and returns no
-    observables."""
+    final one), a few percent of its step time, and the summary counts the requests that failed.
+    reduce=False skips the reductions and returns no observables."""
     order = sorted(requests, key=lambda r: r.arrival)
     t0 = time.perf_counter()
     done_at = {}
+    failed = 0
     for req in order:
         wait = req.arrival - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
         sim = B.Simulation(req.case, stream=stream, reduce=reduce)
         sim.step(req.case.steps)
-        sim.observables()
+        failed += bool(sim.observables()["status"]) if reduce else 0
         sim.close()
         done_at[req.rid] = time.perf_counter() - t0
     wall = time.perf_counter() - t0
-    return _summary(order, done_at, wall)
+    return _summary(order, done_at, wall, **({"failed": failed} if reduce else {}))
 
 
 def _summary(order, done_at, wall, **extra):
@@ -117,12 +121,61 @@ def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4
                              max_resident_nodes=cap)
             print(f"load {load} cap {cap:>8d}: p50 {st['p50_s']:.3f} p99 {st['p99_s']:.3f} "
                   f"mean {st['mean_s']:.3f} max {st['max_s']:.3f} GLUPS {st['aggregate_mlups'] / 1e3:.1f} "
-                  f"running<= {st['max_running']}", flush=True)
+                  f"running<= {st['max_running']} failed {st['failed']}", flush=True)
         if fifo:
             st = run_fifo(reqs)
             print(f"load {load} fifo        : p50 {st['p50_s']:.3f} p99 {st['p99_s']:.3f} "
-                  f"mean {st['mean_s']:.3f} max {st['max_s']:.3f} GLUPS {st['aggregate_mlups'] / 1e3:.1f}",
-                  flush=True)
+                  f"mean {st['mean_s']:.3f} max {st['max_s']:.3f} GLUPS {st['aggregate_mlups'] / 1e3:.1f} "
+                  f"failed {st['failed']}", flush=True)
+
+
+def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30, steps_per_launch=64):
+    """Throughput of a fixed batch: n square requests of one grid (the serving stream's geometry
+    draws, all `steps` long, in `storage`) submitted at once to a pool without an admission cap,
+    against the same requests run one at a time through the single-simulation API without
+    reductions.  A request the pool reports failed (a non-finite or non-positive density) is run
+    alone again with reductions, which must fail the same way.  Returns (pool GLUPS, single GLUPS,
+    number failed)."""
+    import torch
+    from . import inputs as I
+    reqs = I.serving_requests(n=n, nmin=grid, nmax=grid, steps_range=(steps, steps))
+    for r in reqs:
+        r.case.storage = storage
+    lups = sum(r.case.nodes * r.case.steps for r in reqs)
+    pool = B.Pool(budget_bytes, max_slots=max(n, 1), steps_per_launch=steps_per_launch)
+    ids = [pool.submit(r.case, steps) for r in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        running, queued, _ = pool.advance()
+        if running == 0 and queued == 0:
+            break
+    pool_s = time.perf_counter() - t0
+    failed = []
+    for r, rid in zip(reqs, ids):
+        st, _ = pool.status(rid)
+        if st == B.FAILED:
+            failed.append(r)
+        elif st != B.DONE:
+            raise RuntimeError(f"request {r.rid} ended in state {st}")
+    pool.close()
+    sims = [B.Simulation(r.case, stream=None, reduce=False) for r in reqs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(steps)
+    torch.cuda.synchronize()
+    single_s = time.perf_counter() - t0
+    for sim in sims:
+        sim.close()
+    for r in failed:
+        sim = B.Simulation(r.case, stream=None, reduce=True)
+        sim.step(steps)
+        st = sim.observables()["status"]
+        sim.close()
+        if not st:
+            raise RuntimeError(f"request {r.rid} failed in the pool but not alone")
+    return lups / pool_s / 1e9, lups / single_s / 1e9, len(failed)
 
 
 def main():
@@ -135,12 +188,23 @@ def main():
     ap.add_argument("--loads", default="1.2,0.7")
     ap.add_argument("--caps", default="0,1000000,2000000,4000000")
     ap.add_argument("--fifo", action="store_true", help="also run each load one request at a time")
+    ap.add_argument("--batch", default="", metavar="N:GRID:STEPS[:STORAGE],...",
+                    help="fixed batches through the pool against one at a time, e.g. 24:704:2000")
     args = ap.parse_args()
-    if not args.cap_sweep:
-        ap.error("nothing to do (try --cap-sweep)")
+    if not args.cap_sweep and not args.batch:
+        ap.error("nothing to do (try --cap-sweep or --batch)")
     import torch
     torch.cuda.set_device(0)
     B.load()
+    for spec in filter(None, args.batch.split(",")):
+        f = spec.split(":")
+        n, grid, steps = int(f[0]), int(f[1]), int(f[2])
+        storage = f[3] if len(f) > 3 else "f32"
+        pool_g, single_g, nfail = fixed_batch(n, grid, steps, storage)
+        print(f"batch {n} x {grid}^2 {storage} {steps} steps: pool {pool_g:.1f} GLUPS, "
+              f"one at a time {single_g:.1f} GLUPS ({nfail} failed in both)", flush=True)
+    if not args.cap_sweep:
+        return
     cap_sweep(args.capacity_glups, tuple(float(x) for x in args.loads.split(",")),
               tuple(int(x) for x in args.caps.split(",")), fifo=args.fifo)
 

@@ -45,9 +45,11 @@ def run(pool_cls, cases, budget, slots=64, spl=32, max_nodes=0):
     return res, max_running
 
 
-def test_alone_and_in_the_mix_are_bitwise_equal(gpu):
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_alone_and_in_the_mix_are_bitwise_equal(gpu, storage):
+    """FP64 requests (two steps per launch) and binary32 ones (three steps per launch)."""
     B = gpu
-    cases = small_requests()
+    cases = small_requests(storage=storage)
     alone = {k: run(B.Pool, [c], 1 << 30)[0][0] for k, c in enumerate(cases)}
     # a budget that holds about three of them: admission binds, requests queue and overlap
     budget = int(3 * max(B.vplbm_pool_bytes_needed(c) for c in cases))
@@ -250,12 +252,13 @@ def test_stochastic_rounding_is_the_same_in_the_pool(gpu, storage):
 
 @pytest.mark.parametrize("spl", [1, 7, 64])
 def test_launch_shapes_match_the_single_simulation_bitwise(gpu, spl):
-    """The pool takes pairs of steps per launch, an odd one last when steps_per_launch is odd, and
-    a single step for a request with one step left.  Over odd and even step counts and mixed
-    storage formats, the fields are bitwise those of the single-simulation path."""
+    """The pool takes pairs of steps per launch (triples for binary32), what remains of a replay
+    last, and fewer steps for a request with fewer left.  Over step counts of every remainder and
+    mixed storage formats, the fields are bitwise those of the single-simulation path."""
     B = gpu
-    cases = small_requests(seed=13, n=5)
-    for c, st, n in zip(cases, ("f32", "f16s", "f64", "f32d", "bf16sr"), (151, 200, 97, 64, 33)):
+    cases = small_requests(seed=13, n=7)
+    for c, st, n in zip(cases, ("f32", "f16s", "f64", "f32d", "bf16sr", "f32", "f32"),
+                        (151, 200, 97, 64, 33, 100, 65)):
         c.storage = st
         c.steps = n
     res, _ = run(B.Pool, cases, 1 << 30, spl=spl)

@@ -53,19 +53,21 @@ def _drain(pool, ids):
     return out
 
 
-@pytest.mark.parametrize("spl,every", [(64, 256), (7, 280)])
-def test_pool_early_stop(gpu, spl, every):
+@pytest.mark.parametrize("spl,every,storage,tol", [(64, 256, "f64", 1e-6), (7, 280, "f64", 1e-6),
+                                                   (64, 256, "f32", 1e-5), (7, 280, "f32", 1e-5)])
+def test_pool_early_stop(gpu, spl, every, storage, tol):
     """A steady plane-shear run with an early stop retires at the first check whose residual is
     below the tolerance, one step after it; its result is the single-simulation run of as many
     steps.  A run whose tolerance is never met runs all its steps, and a run without a stop is
     not affected.  With an odd steps_per_launch the final step after the stop is the single step
-    of a replay's first launch."""
+    of a replay's first launch.  Binary32 runs take three steps per launch on 14-row tiles."""
     B = gpu
-    tol = 1e-6
     steady = S.shear_case("srt", 0.5 + math.sqrt(6) / 4).case
     never = S.shear_case("mrt", 1.5, 3 / 16, nx=32).case
     plain = I.Case("plain", 90, 60, collision="mrt", tau=0.7, bc=I.CHANNEL, u_in=(0.04, 0.0),
                    u0=(0.04, 0.0), bodies=[I.body("disk", 30, 29.5, r=6)], storage="f64")
+    for c in (steady, never, plain):
+        c.storage = storage
     pool = B.Pool(1 << 30, max_slots=4, steps_per_launch=spl)
     a = pool.submit(steady, 400_000, keep_fields=True, stop=(tol, every))
     b = pool.submit(never, 3 * every, keep_fields=True, stop=(1e-300, every))

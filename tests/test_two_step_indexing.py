@@ -117,15 +117,18 @@ def test_convective_outlet_lookups(tw, th):
         check_lattice(nx, ny, 0, yper, tw, th, outlet=True)
 
 
-def pool_buf(done, spl):
-    """The pool's buffer after `done` steps (pool.hip): launches counted per graph replay."""
-    launches = (done // spl) * ((spl + 1) // 2) + ((done % spl) + 1) // 2
+def pool_buf(done, spl, spk=2):
+    """The pool's buffer after `done` steps (pool.hip): launches of spk steps counted per graph
+    replay, what remains of a replay last."""
+    launches = (done // spl) * (-(-spl // spk)) + -(-(done % spl) // spk)
     return launches & 1
 
 
-def test_pool_buffer_follows_the_launch_sequence():
-    """Replays of spl steps in pairs from the replay's start (an odd one last), a request with one
-    step left taking it alone, and early stops that lower the target to a replay boundary + 1."""
+@pytest.mark.parametrize("spk", [2, 3])
+def test_pool_buffer_follows_the_launch_sequence(spk):
+    """Replays of spl steps in launches of spk from the replay's start (what remains last), a
+    request with fewer steps left than the launch taking those, and early stops that lower the
+    target to a replay boundary + 1."""
     rng = random.Random(1)
     for spl in list(range(1, 12)) + [63, 64]:
         for _ in range(100):
@@ -133,15 +136,15 @@ def test_pool_buffer_follows_the_launch_sequence():
             stop_at = rng.randint(1, max(1, target // spl)) * spl if rng.random() < 0.5 else None
             buf, done, tgt = 0, 0, target
             while done < tgt:
-                for j in range(0, spl, 2):
+                for j in range(0, spl, spk):
                     if done >= tgt:
                         break
-                    n = 2 if spl - j >= 2 else 1
-                    k = 1 if tgt - done < n else n
-                    assert pool_buf(done, spl) == buf
+                    n = min(spk, spl - j)
+                    k = min(n, tgt - done)
+                    assert pool_buf(done, spl, spk) == buf
                     buf ^= 1
                     done += k
-                    assert pool_buf(done, spl) == buf
+                    assert pool_buf(done, spl, spk) == buf
                 if stop_at is not None and done == stop_at and tgt > done + 1:
                     tgt = done + 1
 
