@@ -59,6 +59,7 @@ struct PoolSim {
     int ntx, ntiles;
     int th;                  // tile height (the tile width is kPoolTileW)
     int spk;                 // steps per kernel launch: 3 for binary32, else 2
+    int nt;                  // 1: non-temporal population stores (the resident buffers exceed the cache)
     int active;
     int spl;                 // steps per graph replay (the pool's steps_per_launch)
     long long t0, target;    // pool step at admission; steps to run
@@ -211,8 +212,9 @@ __device__ __forceinline__ bool pool_locate(const Geom &g, int ux, int uy, int h
 // First phase of a multi-step launch on a 64 x kPool3H tile: step `step` on the tile and a halo
 // of H nodes, from the planes in global memory into the LDS tile, whose slots are laid out with a
 // two-node halo (kPool3EW per row) whatever H is.  Returns whether an own node went bad.
-template <int S, int H>
+template <int S, int H, bool inner>
 __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typename Codec<S>::elem *src,
+                                                 __amdgpu_buffer_rsrc_t rsrc,
                                                  typename Codec<S>::elem *mid, int x0, int y0,
                                                  unsigned step)
 {
@@ -223,11 +225,12 @@ __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typenam
     bool bad = false;
     for (int e = threadIdx.x; e < N1; e += kBlock2) {
         const int ux = x0 + e % W1 - H, uy = y0 + e / W1 - H;
-        int x, y;
-        if (!pool_locate(g, ux, uy, H, x, y)) continue;
+        int x = ux, y = uy;
+        if (!inner && !pool_locate(g, ux, uy, H, x, y)) continue;
         T f[9];
         int id;
-        pull<S>(src, x, y, g, none, f);
+        if constexpr (inner) pull_interior_buf<S>(rsrc, g.plane, g.pitch, unsigned(y * g.pitch + x), f);
+        else pull<S>(src, x, y, g, none, f);
         const auto m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
         store_node<S>(mid, kPool3EN, unsigned((uy - y0 + 2) * kPool3EW + (ux - x0 + 2)), f,
                       unsigned(y * g.pitch + x), step);
@@ -245,8 +248,11 @@ __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typenam
 // until every pull is made), step done + 2 of the tile to global memory; for k = 2 the first
 // phase with a one-node halo and the last; for k = 1 the last alone, from global memory.  On the
 // simulation's final step the tile's FP64 sums go to its slot of the partials (per-wave rows
-// added in order, rows in order).
-template <int S>
+// added in order, rows in order).  inner: the tile lies three or more nodes from every edge of a
+// simulation whose planes span less than 4 GB (pool3_inner); then every phase pulls by plain
+// shifts, the first through a buffer resource, and the last stores through one, as the
+// single-simulation three-step kernel does for its inner tiles.
+template <int S, bool inner>
 __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long done, int k,
                                            unsigned char *lds, double (*part)[kRingWidth])
 {
@@ -265,9 +271,12 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool final_step = done + k == d.target;             // uniform over the workgroup
     if (final_step && lane < kRingWidth) part[wave][lane] = 0.0;
+    const unsigned long long pbytes = 9ull * (unsigned long long)g.plane * sizeof(E);
+    const __amdgpu_buffer_rsrc_t rsrc = buffer_over(const_cast<E *>(src), unsigned(pbytes));
+    const __amdgpu_buffer_rsrc_t rdst = buffer_over(dst, unsigned(pbytes));
     bool bad = false;
     if (k == 3) {
-        bad |= pool_first_phase<S, 2>(d, src, mid, x0, y0, (unsigned)done);
+        bad |= pool_first_phase<S, 2, inner>(d, src, rsrc, mid, x0, y0, (unsigned)done);
         __syncthreads();
         constexpr int MW = TW + 2, MN = MW * (TH + 2), R2 = (MN + kBlock2 - 1) / kBlock2;
         T res[R2][9];
@@ -277,12 +286,13 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
         for (int it = 0; it < R2; it++) {
             const int j = threadIdx.x + it * kBlock2;
             const int ux = x0 + j % MW - 1, uy = y0 + j / MW - 1;
-            int x, y;
+            int x = ux, y = uy;
             slot[it] = -1;
             node[it] = 0;
-            if (j < MN && pool_locate(g, ux, uy, 1, x, y)) {
+            if (j < MN && (inner || pool_locate(g, ux, uy, 1, x, y))) {
                 int id;
-                pull_tile<S, 2>(mid, EN, EW, ux, uy, x0, y0, g, res[it]);
+                if constexpr (inner) pull_tile_shifts<S, 2>(mid, EN, EW, ux, uy, x0, y0, res[it]);
+                else pull_tile<S, 2>(mid, EN, EW, ux, uy, x0, y0, g, res[it]);
                 const auto m = relax_node(res[it], d.mask, d.bodies, g, d.p, x, y, id);
                 slot[it] = (j / MW + 1) * EW + j % MW + 1;
                 node[it] = unsigned(y * g.pitch + x);
@@ -298,7 +308,7 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
             if (slot[it] >= 0) store_node<S>(mid, EN, unsigned(slot[it]), res[it], node[it], (unsigned)(done + 1));
         __syncthreads();
     } else if (k == 2) {
-        bad |= pool_first_phase<S, 1>(d, src, mid, x0, y0, (unsigned)done);
+        bad |= pool_first_phase<S, 1, inner>(d, src, rsrc, mid, x0, y0, (unsigned)done);
         __syncthreads();
     }
     constexpr int R3 = (TW * TH + kBlock2 - 1) / kBlock2;
@@ -314,10 +324,13 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
                 m = update_node<S>(src, dst, d.mask, d.bodies, g, none, d.p, x, y, id, (unsigned)done);
             } else {
                 T f[9];
-                pull_tile<S, 2>(mid, EN, EW, x, y, x0, y0, g, f);
+                if constexpr (inner) pull_tile_shifts<S, 2>(mid, EN, EW, x, y, x0, y0, f);
+                else pull_tile<S, 2>(mid, EN, EW, x, y, x0, y0, g, f);
                 m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
                 const unsigned i = y * g.pitch + x;
-                store_node<S>(dst, g.plane, i, f, i, (unsigned)(done + k - 1));
+                if constexpr (!inner) store_node<S>(dst, g.plane, i, f, i, (unsigned)(done + k - 1));
+                else if (d.nt) store_node_buf<S, true>(rdst, g.plane, i, f);
+                else store_node_buf<S, false>(rdst, g.plane, i, f);
             }
             rho = 1.0 + double(m.drho);
             fx = double(m.fx);
@@ -354,6 +367,15 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
     }
 }
 
+// Whether binary32 tile `tile` of d takes pool_tile3's inner form.
+__device__ __forceinline__ bool pool3_inner(const PoolSim &d, int tile)
+{
+    const Geom &g = d.g;
+    const int x0 = (tile % d.ntx) * kPoolTileW, y0 = (tile / d.ntx) * kPool3H;
+    return (x0 >= 3) & (x0 + kPoolTileW + 3 <= g.nx) & (y0 >= 3) & (y0 + kPool3H + 3 <= g.ny) &
+           (9ull * (unsigned long long)g.plane * 4ull <= 0xFFFFFFFFull);
+}
+
 // Storage formats by kernel: class 1 computes in FP64 (F64, F32D), class 0 in FP32 with 2-byte
 // storage, both two steps per launch; class 2 is binary32 storage, three steps per launch.  Each
 // class has a kernel of its own, so the FP32 formats are not held to the FP64 path's registers
@@ -388,7 +410,8 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     if (pool_class(d.storage) != CLASS) return;
     const int k = d.target - done < nsteps ? int(d.target - done) : nsteps;
     if constexpr (CLASS == 2) {
-        pool_tile3<kF32>(d, tr.tile, done, k, lds, part);
+        if (pool3_inner(d, tr.tile)) pool_tile3<kF32, true>(d, tr.tile, done, k, lds, part);
+        else pool_tile3<kF32, false>(d, tr.tile, done, k, lds, part);
     } else if constexpr (CLASS == 1) {
         if (d.storage == kF64) pool_tile<kF64>(d, tr.tile, done, k, lds, part);
         else pool_tile<kF32D>(d, tr.tile, done, k, lds, part);
@@ -859,11 +882,17 @@ int ensure_pool_graph(vplbm_pool p)
 int upload_tables(vplbm_pool p)
 {
     std::vector<TileRef> tiles;
+    uint64_t pop_bytes = 0;   // both population buffers of every resident simulation
     for (int s = 0; s < p->cfg.max_slots; s++) {
         const PoolSim &d = p->h_sims[s];
         if (!d.active) continue;
         for (int t = 0; t < d.ntiles; t++) tiles.push_back({s, t});
+        pop_bytes += (uint64_t)2 * 9 * d.g.plane * elem_bytes(d.storage);
     }
+    // Non-temporal stores once the resident populations exceed what the cache keeps (the rule of
+    // a single simulation, applied to the whole pool: every launch reads them all again).
+    for (int s = 0; s < p->cfg.max_slots; s++)
+        if (p->h_sims[s].active) p->h_sims[s].nt = pop_bytes > ((uint64_t)192 << 20) ? 1 : 0;
     if ((int)tiles.size() > p->tile_cap) {
         HIP_TRY(hipStreamSynchronize(p->stream));
         if (p->d_tiles) HIP_TRY(hipFree(p->d_tiles));

@@ -131,11 +131,12 @@ def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4
 
 def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30, steps_per_launch=64):
     """Throughput of a fixed batch: n square requests of one grid (the serving stream's geometry
-    draws, all `steps` long, in `storage`) submitted at once to a pool without an admission cap,
-    against the same requests run one at a time through the single-simulation API without
-    reductions.  A request the pool reports failed (a non-finite or non-positive density) is run
-    alone again with reductions, which must fail the same way.  Returns (pool GLUPS, single GLUPS,
-    number failed)."""
+    draws, all `steps` long, in `storage`) submitted at once to a pool without an admission cap;
+    the same requests through the single-simulation API without reductions, one at a time (each
+    finished before the next starts), and all at once, each simulation on a stream of its own.
+    A request the pool reports failed (a non-finite or non-positive density) is run alone again
+    with reductions, which must fail the same way.  Returns GLUPS of the pool, one at a time and
+    the concurrent streams, and the number failed."""
     import torch
     from . import inputs as I
     reqs = I.serving_requests(n=n, nmin=grid, nmax=grid, steps_range=(steps, steps))
@@ -159,13 +160,22 @@ def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30, steps_per_l
         elif st != B.DONE:
             raise RuntimeError(f"request {r.rid} ended in state {st}")
     pool.close()
+    sims = [B.Simulation(r.case, stream=None, reduce=False) for r in reqs]   # a stream each
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sim in sims:
+        sim.step(steps)
+        torch.cuda.synchronize()
+    single_s = time.perf_counter() - t0
+    for sim in sims:
+        sim.close()
     sims = [B.Simulation(r.case, stream=None, reduce=False) for r in reqs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for sim in sims:
         sim.step(steps)
     torch.cuda.synchronize()
-    single_s = time.perf_counter() - t0
+    streams_s = time.perf_counter() - t0
     for sim in sims:
         sim.close()
     for r in failed:
@@ -175,7 +185,7 @@ def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30, steps_per_l
         sim.close()
         if not st:
             raise RuntimeError(f"request {r.rid} failed in the pool but not alone")
-    return lups / pool_s / 1e9, lups / single_s / 1e9, len(failed)
+    return lups / pool_s / 1e9, lups / single_s / 1e9, lups / streams_s / 1e9, len(failed)
 
 
 def main():
@@ -200,9 +210,10 @@ def main():
         f = spec.split(":")
         n, grid, steps = int(f[0]), int(f[1]), int(f[2])
         storage = f[3] if len(f) > 3 else "f32"
-        pool_g, single_g, nfail = fixed_batch(n, grid, steps, storage)
+        pool_g, single_g, streams_g, nfail = fixed_batch(n, grid, steps, storage)
         print(f"batch {n} x {grid}^2 {storage} {steps} steps: pool {pool_g:.1f} GLUPS, "
-              f"one at a time {single_g:.1f} GLUPS ({nfail} failed in both)", flush=True)
+              f"one at a time {single_g:.1f}, concurrent streams {streams_g:.1f} "
+              f"({nfail} failed in both)", flush=True)
     if not args.cap_sweep:
         return
     cap_sweep(args.capacity_glups, tuple(float(x) for x in args.loads.split(",")),
