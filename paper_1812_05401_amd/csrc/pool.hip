@@ -60,6 +60,9 @@ struct PoolSim {
     int th;                  // tile height (the tile width is kPoolTileW)
     int spk;                 // steps per kernel launch: 3 for binary32, else 2
     int nt;                  // 1: non-temporal population stores (the resident buffers exceed the cache)
+    int conv;                // 1: convective outlet at x = nx - 1
+    double ou;               // its convection speed (the inlet speed)
+    void *outlet[2];         // its recorded values (3 x ny, compute type) per buffer parity
     int active;
     int spl;                 // steps per graph replay (the pool's steps_per_launch)
     long long t0, target;    // pool step at admission; steps to run
@@ -120,19 +123,28 @@ __device__ __forceinline__ void pool_tile_partials(const PoolSim &d, int tile, d
 
 // One tile of one simulation for `nsteps` (1 or 2) steps from `done`: the node arithmetic of the
 // single-simulation kernels (update_node, or the two-step form with the first step kept in LDS),
-// so a simulation's fields do not depend on the launch shape or its co-residents.
-template <int S>
+// so a simulation's fields do not depend on the launch shape or its co-residents.  CONV: the
+// simulation has a convective outlet; as in the single-simulation two-step kernel, the first step
+// reads the previous values from global memory and keeps what it records for the tile's rows in
+// LDS (outl, 3 x kPoolTileH values), and the second applies the outlet rule with them and records
+// its own for the next launch.
+template <int S, bool CONV>
 __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long done, int nsteps,
-                                          unsigned char *lds, double (*part)[kRingWidth])
+                                          unsigned char *lds, double (*part)[kRingWidth],
+                                          double *outl_lds)
 {
     using C = Codec<S>;
     using T = typename C::real;
     using E = typename C::elem;
+    constexpr int odirs[3] = {3, 6, 7};           // the directions entering from x = nx
     const Geom &g = d.g;
     const int b = pool_buf(done, d.spl, d.spk);
     const E *__restrict__ src = static_cast<const E *>(d.buf[b]);
     E *__restrict__ dst = static_cast<E *>(d.buf[b ^ 1]);
     const Outlet none{nullptr, nullptr, 0.0};
+    const Outlet one{CONV ? d.outlet[b] : nullptr, CONV ? d.outlet[b ^ 1] : nullptr, d.ou};
+    const Outlet out1{CONV ? d.outlet[b] : nullptr, nullptr, d.ou};
+    T *outl = reinterpret_cast<T *>(outl_lds);
     const int x0 = (tile % d.ntx) * kPoolTileW, y0 = (tile / d.ntx) * kPoolTileH;
     const int x = x0 + (threadIdx.x % kPoolTileW), y = y0 + (threadIdx.x / kPoolTileW);
     const bool active = (x < g.nx) & (y < g.ny);
@@ -141,7 +153,8 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
     bool bad = false;
     if (nsteps == 1) {
         if (active) {
-            const auto m = update_node<S>(src, dst, d.mask, d.bodies, g, none, d.p, x, y, id, (unsigned)done);
+            const auto m = update_node<S>(src, dst, d.mask, d.bodies, g, CONV ? one : none, d.p, x, y, id,
+                                          (unsigned)done);
             rho = 1.0 + double(m.drho);
             fx = double(m.fx);
             fy = double(m.fy);
@@ -165,11 +178,13 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
             if (live) {
                 T f[9];
                 int hid;
-                pull<S>(src, hx, hy, g, none, f);
-                const auto m = relax_node(f, d.mask, d.bodies, g, d.p, hx, hy, hid);
-                store_node<S>(mid, kPoolEN, unsigned(e), f, unsigned(hy * g.pitch + hx), (unsigned)done);
                 const bool own = (lx >= 0) & (lx < kPoolTileW) & (ly >= 0) & (ly < kPoolTileH) &
                                  (x0 + lx < g.nx) & (y0 + ly < g.ny);
+                pull<S>(src, hx, hy, g, CONV ? out1 : none, f);
+                if (CONV && hx == g.nx - 1 && own)
+                    for (int k = 0; k < 3; k++) outl[k * kPoolTileH + ly] = f[odirs[k]];
+                const auto m = relax_node(f, d.mask, d.bodies, g, d.p, hx, hy, hid);
+                store_node<S>(mid, kPoolEN, unsigned(e), f, unsigned(hy * g.pitch + hx), (unsigned)done);
                 const double r1 = 1.0 + double(m.drho);
                 bad |= own && !(r1 > 0.0 && r1 < 1e30);
             }
@@ -178,6 +193,18 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
         if (active) {
             T f[9];
             pull_tile<S>(mid, kPoolEN, kPoolEW, x, y, x0, y0, g, f);
+            if (CONV && x == g.nx - 1) {
+                // the outlet rule of pull, with the first step's values from LDS
+                const T u = T(d.ou);
+                T *next = static_cast<T *>(d.outlet[b ^ 1]);
+                for (int k = 0; k < 3; k++) {
+                    int pa;
+                    const unsigned jn = tile_source(odirs[k], g.nx - 2, y, x0, y0, kPoolEW, g, pa);
+                    const T nb = C::load(mid + pa * kPoolEN, jn, weight<T>(odirs[k]));
+                    f[odirs[k]] = (outl[k * kPoolTileH + (y - y0)] + u * nb) / (T(1) + u);
+                }
+                for (int k = 0; k < 3; k++) next[k * g.ny + y] = f[odirs[k]];
+            }
             const auto m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
             const unsigned i = y * g.pitch + x;
             store_node<S>(dst, g.plane, i, f, i, (unsigned)(done + 1));
@@ -380,14 +407,24 @@ __device__ __forceinline__ bool pool3_inner(const PoolSim &d, int tile)
 // storage, both two steps per launch; class 2 is binary32 storage, three steps per launch.  Each
 // class has a kernel of its own, so the FP32 formats are not held to the FP64 path's registers
 // and LDS: measured 4 waves per SIMD with one kernel for all.
-__host__ __device__ inline int pool_class(int storage)
+__host__ __device__ inline int pool_class(int storage, int conv)
 {
-    return storage == kF64 || storage == kF32D ? 1 : (storage == kF32 ? 2 : 0);
+    return storage == kF64 || storage == kF32D ? 1 : (storage == kF32 && !conv ? 2 : 0);
 }
 
 // Tile height and steps per kernel launch of a storage format's class.
-__host__ __device__ inline int pool_tile_h(int storage) { return pool_class(storage) == 2 ? kPool3H : kPoolTileH; }
-__host__ __device__ inline int pool_spk(int storage) { return pool_class(storage) == 2 ? 3 : 2; }
+__host__ __device__ inline int pool_tile_h(int storage, int conv) { return pool_class(storage, conv) == 2 ? kPool3H : kPoolTileH; }
+__host__ __device__ inline int pool_spk(int storage, int conv) { return pool_class(storage, conv) == 2 ? 3 : 2; }
+
+// pool_tile with or without the convective outlet (a separate instantiation, as in the
+// single-simulation two-step kernel).
+template <int S>
+__device__ __forceinline__ void pool_tile2(const PoolSim &d, int tile, long long done, int nsteps,
+                                           unsigned char *lds, double (*part)[kRingWidth], double *outl)
+{
+    if (d.conv) pool_tile<S, true>(d, tile, done, nsteps, lds, part, outl);
+    else pool_tile<S, false>(d, tile, done, nsteps, lds, part, outl);
+}
 
 // Steps t_off .. t_off + nsteps - 1 of the graph replay (nsteps up to the class's steps per
 // launch), for every resident simulation of class CLASS: workgroup w (< *ntiles) updates one tile
@@ -401,26 +438,28 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     // the LDS tile in the class's widest storage format
     __shared__ __align__(16) unsigned char lds[CLASS == 2 ? 9 * kPool3EN * 4 : 9 * kPoolEN * (CLASS ? 8 : 4)];
     __shared__ double part[kBlock2 / 64][kRingWidth];
+    __shared__ double outl[3 * kPoolTileH];                   // convective outlet (pool_tile)
     const int n = *ntiles;
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
     const TileRef tr = tiles[xcd_tile(blockIdx.x, n)];
     const PoolSim &d = sims[tr.slot];
     const long long done = *t_base + t_off - d.t0;
     if (!d.active || done < 0 || done >= d.target) return;    // uniform over the workgroup
-    if (pool_class(d.storage) != CLASS) return;
+    if (pool_class(d.storage, d.conv) != CLASS) return;
     const int k = d.target - done < nsteps ? int(d.target - done) : nsteps;
     if constexpr (CLASS == 2) {
         if (pool3_inner(d, tr.tile)) pool_tile3<kF32, true>(d, tr.tile, done, k, lds, part);
         else pool_tile3<kF32, false>(d, tr.tile, done, k, lds, part);
     } else if constexpr (CLASS == 1) {
-        if (d.storage == kF64) pool_tile<kF64>(d, tr.tile, done, k, lds, part);
-        else pool_tile<kF32D>(d, tr.tile, done, k, lds, part);
+        if (d.storage == kF64) pool_tile2<kF64>(d, tr.tile, done, k, lds, part, outl);
+        else pool_tile2<kF32D>(d, tr.tile, done, k, lds, part, outl);
     } else {
         switch (d.storage) {
-        case kF16S: pool_tile<kF16S>(d, tr.tile, done, k, lds, part); break;
-        case kF16SR: pool_tile<kF16SR>(d, tr.tile, done, k, lds, part); break;
-        case kBF16SR: pool_tile<kBF16SR>(d, tr.tile, done, k, lds, part); break;
-        default: pool_tile<kBF16S>(d, tr.tile, done, k, lds, part); break;
+        case kF32: pool_tile<kF32, true>(d, tr.tile, done, k, lds, part, outl); break;   // outlet only
+        case kF16S: pool_tile2<kF16S>(d, tr.tile, done, k, lds, part, outl); break;
+        case kF16SR: pool_tile2<kF16SR>(d, tr.tile, done, k, lds, part, outl); break;
+        case kBF16SR: pool_tile2<kBF16SR>(d, tr.tile, done, k, lds, part, outl); break;
+        default: pool_tile2<kBF16S>(d, tr.tile, done, k, lds, part, outl); break;
         }
     }
 }
@@ -449,9 +488,9 @@ __device__ __forceinline__ void pool_residual_node(const PoolSim &d, int parity,
                                                    double &d2, double &u2)
 {
     using E = typename Codec<S>::elem;
-    const Outlet none{nullptr, nullptr, 0.0};
+    const Outlet o{d.conv ? d.outlet[parity] : nullptr, nullptr, d.ou};   // read, not recorded
     int id;
-    const auto m = observe_node<S>(static_cast<const E *>(d.buf[parity]), d.mask, d.bodies, d.g, none, d.p, x, y, id);
+    const auto m = observe_node<S>(static_cast<const E *>(d.buf[parity]), d.mask, d.bodies, d.g, o, d.p, x, y, id);
     const size_t n = (size_t)d.g.nx * d.g.ny, i = (size_t)y * d.g.nx + x;
     const double ux = double(m.ux), uy = double(m.uy);
     if (id == 0) {
@@ -565,6 +604,7 @@ struct Request {
     double *partials = nullptr;
     double *snap = nullptr;
     double *rpart = nullptr;
+    void *outlet[2] = {nullptr, nullptr};
 };
 
 int pool_geometry(const vplbm_config &c, Geom &g, int &ntx, int &ntiles)
@@ -576,7 +616,7 @@ int pool_geometry(const vplbm_config &c, Geom &g, int &ntx, int &ntiles)
     g.xper = c.bc_xlo == VPLBM_PERIODIC;
     g.yper = c.bc_ylo == VPLBM_PERIODIC;
     g.inlet = c.bc_xlo == VPLBM_VELOCITY;
-    const int th = pool_tile_h(c.storage);
+    const int th = pool_tile_h(c.storage, c.bc_xhi == VPLBM_CONVECTIVE);
     ntx = (c.nx + kPoolTileW - 1) / kPoolTileW;
     ntiles = ntx * ((c.ny + th - 1) / th);
     return VPLBM_OK;
@@ -589,8 +629,10 @@ uint64_t bytes_needed(const vplbm_config &c, bool stop = false)
     pool_geometry(c, g, ntx, ntiles);
     const uint64_t pop = (uint64_t)9 * g.plane * elem_bytes(c.storage);
     const uint64_t residual = stop ? 2 * (uint64_t)g.nx * g.ny * sizeof(double) + (uint64_t)ntiles * 2 * sizeof(double) : 0;
+    const uint64_t outlet = c.bc_xhi == VPLBM_CONVECTIVE ? 2 * 3 * (uint64_t)g.ny * sizeof(double) : 0;
     return 2 * pop + (uint64_t)g.pitch * g.ny + sizeof(BodyParams) * kMaxBodies +
-           sizeof(BodyState) * kMaxBodies + (uint64_t)ntiles * kRingWidth * sizeof(double) + residual;
+           sizeof(BodyState) * kMaxBodies + (uint64_t)ntiles * kRingWidth * sizeof(double) + residual +
+           outlet;
 }
 
 std::mutex g_pool_mu;
@@ -640,9 +682,11 @@ bool pool_valid(const void *p)
 
 void free_request_memory(vplbm_pool p, Request &r)
 {
-    void *ptrs[] = {r.buf[0], r.buf[1], r.mask, r.params, r.state_dev, r.partials, r.snap, r.rpart};
+    void *ptrs[] = {r.buf[0], r.buf[1], r.mask, r.params, r.state_dev, r.partials, r.snap, r.rpart,
+                    r.outlet[0], r.outlet[1]};
     for (void *q : ptrs)
         if (q) (void)hipFreeAsync(q, p->stream);
+    r.outlet[0] = r.outlet[1] = nullptr;
     r.snap = nullptr;
     r.rpart = nullptr;
     r.buf[0] = r.buf[1] = nullptr;
@@ -700,7 +744,10 @@ int retire(vplbm_pool p, int slot)
         r.ux.resize(n);
         r.uy.resize(n);
         StepArgs a{};
-        a.src = d.buf[pool_buf(done, d.spl, d.spk)];   // the state after `done` steps
+        const int pb = pool_buf(done, d.spl, d.spk);
+        a.src = d.buf[pb];                          // the state after `done` steps
+        a.outlet.prev = d.conv ? d.outlet[pb] : nullptr;
+        a.outlet.u = d.ou;
         a.mask = d.mask;
         a.bodies = d.bodies;
         a.t_base = p->d_zero;
@@ -741,6 +788,7 @@ int admit(vplbm_pool p, Request &r, int slot)
     if (!may_admit(st, r.bytes, nodes)) return 0;
     PoolSim d{};
     pool_geometry(r.cfg, d.g, d.ntx, d.ntiles);
+    const int conv = r.cfg.bc_xhi == VPLBM_CONVECTIVE ? 1 : 0;
     const size_t pop = (size_t)9 * d.g.plane * elem_bytes(r.cfg.storage);
     struct { void **ptr; size_t n; } allocs[] = {
         {&r.buf[0], pop}, {&r.buf[1], pop}, {(void **)&r.mask, (size_t)d.g.pitch * d.g.ny},
@@ -749,6 +797,8 @@ int admit(vplbm_pool p, Request &r, int slot)
         {(void **)&r.partials, (size_t)d.ntiles * kRingWidth * sizeof(double)},
         {(void **)&r.snap, r.tol > 0.0 ? 2 * (size_t)d.g.nx * d.g.ny * sizeof(double) : 0},
         {(void **)&r.rpart, r.tol > 0.0 ? (size_t)d.ntiles * 2 * sizeof(double) : 0},
+        {&r.outlet[0], conv ? 3 * (size_t)d.g.ny * sizeof(double) : 0},
+        {&r.outlet[1], conv ? 3 * (size_t)d.g.ny * sizeof(double) : 0},
     };
     for (auto &a : allocs) {
         if (a.n == 0) continue;
@@ -776,8 +826,12 @@ int admit(vplbm_pool p, Request &r, int slot)
     d.partials = r.partials;
     d.p = node_params(r.cfg);
     d.storage = r.cfg.storage;
-    d.th = pool_tile_h(d.storage);
-    d.spk = pool_spk(d.storage);
+    d.conv = conv;
+    d.ou = r.cfg.u_in_x;
+    d.outlet[0] = r.outlet[0];
+    d.outlet[1] = r.outlet[1];
+    d.th = pool_tile_h(d.storage, conv);
+    d.spk = pool_spk(d.storage, conv);
     d.active = 1;
     d.spl = p->cfg.steps_per_launch;
     d.t0 = p->t_host;
@@ -795,6 +849,10 @@ int admit(vplbm_pool p, Request &r, int slot)
     a.g = d.g;
     a.p = d.p;
     HIP_TRY(launch_init(d.storage, a, nullptr, nullptr, nullptr, r.cfg.rho0, r.cfg.ux0, r.cfg.uy0, p->stream));
+    if (conv) {   // the previous-step outlet values start as the initial state's last column
+        a.src = d.buf[0];
+        HIP_TRY(launch_outlet_init(d.storage, a, d.outlet[0], p->stream));
+    }
     // the body table copy above reads `hp` from the stack: let it land before returning
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->h_sims[slot] = d;
@@ -814,7 +872,7 @@ int ensure_pool_graph(vplbm_pool p)
     int classes = 0;                      // bit c: a simulation of class c is resident
     for (const PoolSim &d : p->h_sims) {
         checks |= d.active && d.tol > 0.0;
-        if (d.active) classes |= 1 << pool_class(d.storage);
+        if (d.active) classes |= 1 << pool_class(d.storage, d.conv);
     }
     if (!classes) classes = 1;
     if (p->graph && p->grid_cap >= p->ntiles && p->grid_cap <= 8 * (p->ntiles > 4096 ? p->ntiles : 4096) &&
@@ -996,7 +1054,6 @@ int vplbm_pool_submit(vplbm_pool p, const vplbm_config *cfg, const vplbm_body *b
         if (bodies[k].freq != 0.0 && (bodies[k].ax != 0.0 || bodies[k].ay != 0.0))
             return fail(VPLBM_EINVAL, "pool simulations take static bodies only (body %d moves)", k);
     if (nsteps < 1) return fail(VPLBM_EINVAL, "nsteps must be >= 1");
-    if (cfg->bc_xhi == VPLBM_CONVECTIVE) return fail(VPLBM_EINVAL, "pool simulations take the zero-gradient outlet, not the convective one");
     const uint64_t need = bytes_needed(*cfg);
     if (need > p->cfg.budget_bytes)
         return fail(VPLBM_EBUDGET, "simulation needs %llu bytes, pool budget is %llu", (unsigned long long)need, (unsigned long long)p->cfg.budget_bytes);

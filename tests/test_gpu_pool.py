@@ -272,3 +272,61 @@ def test_launch_shapes_match_the_single_simulation_bitwise(gpu, spl):
         for a, b in zip(fields, sfields):
             assert np.array_equal(a, b), f"{c.name}/{c.storage}, {c.steps} steps, {spl} per launch"
         assert abs(obs["mass"] - so["mass"]) <= 1e-13 * so["mass"]
+
+
+def convective_requests(seed, storages, steps):
+    """small_requests on channels with the convective outlet (Section 3.3's outlet)."""
+    cases = small_requests(seed=seed, n=len(storages))
+    for c, st, n in zip(cases, storages, steps):
+        c.bc = I.CHANNEL_CONVECTIVE
+        c.u_in = (0.04, 0.0)
+        c.u0 = (0.04, 0.0)
+        c.storage = st
+        c.steps = n
+    return cases
+
+
+@pytest.mark.parametrize("spl", [1, 7, 64])
+def test_convective_outlet_matches_the_single_simulation_bitwise(gpu, spl):
+    """Requests with a convective outlet take pairs of steps per launch in the pool (binary32 too:
+    the outlet keeps it off the three-step tiles), the outlet's recorded values following the
+    population buffers.  Over step counts of both parities and the storage formats, alone and in
+    a mix with outlet-free requests, the fields are bitwise those of the single-simulation path."""
+    B = gpu
+    conv = convective_requests(17, ("f32", "f64", "f16s", "f32d", "bf16sr", "f16sr"),
+                               (151, 200, 97, 64, 33, 101))
+    plain = small_requests(seed=19, n=3, storage="f32")
+    res, _ = run(B.Pool, conv + plain, 1 << 30, spl=spl)
+    alone = {k: run(B.Pool, [c], 1 << 30, spl=spl)[0][0] for k, c in enumerate(conv[:2])}
+    for k, c in enumerate(conv + plain):
+        obs, fields = res[k]
+        assert obs["status"] == 0 and obs["step"] == c.steps - 1
+        s = B.Simulation(c, stream=None)
+        s.step(c.steps)
+        so, *sfields = s.observables(fields=True)
+        s.close()
+        for a, b in zip(fields, sfields):
+            assert np.array_equal(a, b), f"{c.name}/{c.storage}, {c.steps} steps, {spl} per launch"
+        assert abs(obs["mass"] - so["mass"]) <= 1e-13 * so["mass"]
+        if k in alone:
+            for a, b in zip(alone[k][1], fields):
+                assert np.array_equal(a, b)
+
+
+def test_convective_outlet_in_the_pool_matches_the_oracle(gpu):
+    """FP64 requests with the convective outlet against the oracle (its outlet reading) to 1e-12."""
+    B = gpu
+    cases = convective_requests(23, ("f64", "f64"), (300, 257))
+    res, _ = run(B.Pool, cases, 1 << 30, spl=16)
+    for k, c in enumerate(cases):
+        obs, (rho, ux, uy) = res[k]
+        o = oracle_sim(c)
+        o.step(c.steps)
+        oo = o.obs()
+        orho, oux, ouy = o.fields()
+        assert rel_err(rho, orho) <= 1e-12
+        assert rel_err(np.stack([ux, uy]), np.stack([oux, ouy])) <= 1e-12
+        assert abs(obs["mass"] - oo["mass"]) <= 1e-12 * oo["mass"]
+        sc = force_scale(oo)
+        assert np.max(np.abs(obs["fx"] - oo["fx"])) <= 1e-12 * sc
+        assert np.max(np.abs(obs["fy"] - oo["fy"])) <= 1e-12 * sc

@@ -128,3 +128,35 @@ def test_pool_stop_arguments(gpu):
         B.check(B.load().vplbm_pool_set_stop(pool.h, rid, 1e-6, 10))
     assert e.value.code == B.ESTATE
     pool.close()
+
+
+def test_pool_early_stop_with_convective_outlet(gpu):
+    """A steady low-Reynolds channel flow past a disk with the convective outlet stops at the
+    first check below the tolerance; the pool's residual (which reads the outlet's recorded
+    values) and fields are those of the single-simulation run."""
+    B = gpu
+    tol, every = 1e-7, 256                      # checks fall on graph-replay boundaries (64 steps)
+    case = I.Case("conv_steady", 90, 60, collision="mrt", tau=0.7, bc=I.CHANNEL_CONVECTIVE,
+                  u_in=(0.04, 0.0), u0=(0.04, 0.0), bodies=[I.body("disk", 30, 29.5, r=6)],
+                  storage="f64")
+    pool = B.Pool(1 << 30, max_slots=2, steps_per_launch=64)
+    a = pool.submit(case, 400_000, keep_fields=True, stop=(tol, every))
+    st, done, r, obs, (rho, ux, uy) = _drain(pool, [a])[a]
+    pool.close()
+    assert st == B.DONE and done < 400_000
+    check = done - 1
+    assert check % every == 0 and check >= 3 * every and r < tol
+    print(f"convective channel stopped after {done} steps, residual {r:.3e}", flush=True)
+    s = B.Simulation(case, stream=None)
+    s.step(check - 2 * every)
+    s.residual()
+    s.step(every)
+    r_prev = s.residual()
+    s.step(every)
+    r_single = s.residual()
+    s.step(1)
+    so, srho, sux, suy = s.observables(fields=True)
+    s.close()
+    assert r_prev >= tol
+    assert abs(r_single - r) <= 1e-9 * r
+    assert np.array_equal(rho, srho) and np.array_equal(ux, sux) and np.array_equal(uy, suy)
