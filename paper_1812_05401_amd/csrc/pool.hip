@@ -236,6 +236,34 @@ __device__ __forceinline__ bool pool_locate(const Geom &g, int ux, int uy, int h
     return true;
 }
 
+// pull_interior_buf and store_node_buf (binary32) for the pool, with each plane's scalar offset
+// passed through readfirstlane.  The offsets are uniform over the workgroup (the simulation's
+// pitch and plane size); stated so, the compiler keeps them in scalar registers instead of
+// wrapping each buffer access in a loop over distinct lane values.
+__device__ __forceinline__ void pool_pull_buf(__amdgpu_buffer_rsrc_t r, unsigned plane, unsigned pitch,
+                                              unsigned i, float f[9])
+{
+    const int v = int(i * 4u);
+    const int P = int(pitch);
+    const int shift[9] = {0, -1, -P, 1, P, -P - 1, -P + 1, P + 1, P - 1};
+#pragma unroll
+    for (int a = 0; a < 9; a++) {
+        const int so = __builtin_amdgcn_readfirstlane(int((unsigned(a) * plane + unsigned(shift[a])) * 4u));
+        f[a] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, v, so, 0));
+    }
+}
+
+template <bool NT>
+__device__ __forceinline__ void pool_store_buf(__amdgpu_buffer_rsrc_t r, unsigned plane, unsigned i,
+                                               const float f[9])
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const int so = __builtin_amdgcn_readfirstlane(int(unsigned(k) * plane * 4u));
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f[k]), r, int(i * 4u), so, NT ? 2 : 0);   // 2: nt
+    }
+}
+
 // First phase of a multi-step launch on a 64 x kPool3H tile: step `step` on the tile and a halo
 // of H nodes, from the planes in global memory into the LDS tile, whose slots are laid out with a
 // two-node halo (kPool3EW per row) whatever H is.  Returns whether an own node went bad.
@@ -256,7 +284,7 @@ __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typenam
         if (!inner && !pool_locate(g, ux, uy, H, x, y)) continue;
         T f[9];
         int id;
-        if constexpr (inner) pull_interior_buf<S>(rsrc, g.plane, g.pitch, unsigned(y * g.pitch + x), f);
+        if constexpr (inner) pool_pull_buf(rsrc, g.plane, g.pitch, unsigned(y * g.pitch + x), f);
         else pull<S>(src, x, y, g, none, f);
         const auto m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
         store_node<S>(mid, kPool3EN, unsigned((uy - y0 + 2) * kPool3EW + (ux - x0 + 2)), f,
@@ -356,8 +384,8 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
                 m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
                 const unsigned i = y * g.pitch + x;
                 if constexpr (!inner) store_node<S>(dst, g.plane, i, f, i, (unsigned)(done + k - 1));
-                else if (d.nt) store_node_buf<S, true>(rdst, g.plane, i, f);
-                else store_node_buf<S, false>(rdst, g.plane, i, f);
+                else if (d.nt) pool_store_buf<true>(rdst, g.plane, i, f);
+                else pool_store_buf<false>(rdst, g.plane, i, f);
             }
             rho = 1.0 + double(m.drho);
             fx = double(m.fx);
@@ -427,8 +455,11 @@ __device__ __forceinline__ void pool_tile2(const PoolSim &d, int tile, long long
 }
 
 // Steps t_off .. t_off + nsteps - 1 of the graph replay (nsteps up to the class's steps per
-// launch), for every resident simulation of class CLASS: workgroup w (< *ntiles) updates one tile
-// (tiles of the other classes return at once); a simulation with fewer steps left takes those.
+// launch), for every resident simulation of class CLASS: workgroup w (< *ntiles) updates tile
+// entry w (tiles of the other classes return at once); a simulation with fewer steps left takes
+// those.  The host writes the table in XCD order (upload_tables), so the entry is found without
+// first reading the tile count: the two loads are issued together, and a workgroup starts with
+// two dependent loads (its entry, then its simulation's descriptor) before its populations.
 template <int CLASS>
 __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const TileRef *tiles,
                                                             const int *ntiles,
@@ -440,8 +471,8 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     __shared__ double part[kBlock2 / 64][kRingWidth];
     __shared__ double outl[3 * kPoolTileH];                   // convective outlet (pool_tile)
     const int n = *ntiles;
+    const TileRef tr = tiles[blockIdx.x];                     // the table spans the grid
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
-    const TileRef tr = tiles[xcd_tile(blockIdx.x, n)];
     const PoolSim &d = sims[tr.slot];
     const long long done = *t_base + t_off - d.t0;
     if (!d.active || done < 0 || done >= d.target) return;    // uniform over the workgroup
@@ -464,15 +495,22 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     }
 }
 
-// Final observables of the simulation in `slot`: its tiles' partial sums added in tile order.
-__global__ void pool_fold_kernel(PoolSim *sims, int slot)
+// Final observables of the simulation in `slot`: value q (workgroup q) of its tiles' partial
+// sums.  Thread j adds tiles j, j + 256, ... in order, a fixed butterfly adds each wave's lanes and
+// thread 0 the four waves in order, so the result depends only on the simulation's own tiles.
+constexpr int kFoldBlock = 256;
+__global__ __launch_bounds__(kFoldBlock) void pool_fold_kernel(PoolSim *sims, int slot)
 {
-    PoolSim &d = sims[slot];
-    if (threadIdx.x < kRingWidth) {
-        double v = 0.0;
-        for (int t = 0; t < d.ntiles; t++) v += d.partials[(size_t)t * kRingWidth + threadIdx.x];
-        d.obs[threadIdx.x] = v;
-    }
+    __shared__ double ws[kFoldBlock / 64];
+    const int q = blockIdx.x;
+    const int nt = sims[slot].ntiles;
+    const double *part = sims[slot].partials;
+    double v = 0.0;
+    for (int t = threadIdx.x; t < nt; t += kFoldBlock) v += part[(size_t)t * kRingWidth + q];
+    v = wave_sum<false>(v);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) sims[slot].obs[q] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
 // Whether a simulation checks its residual after this launch (the same test in both kernels).
@@ -511,7 +549,7 @@ __global__ __launch_bounds__(kBlock2) void pool_residual_kernel(PoolSim *sims, c
     const int n = *ntiles;
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const TileRef tr = tiles[xcd_tile(blockIdx.x, n)];
+    const TileRef tr = tiles[blockIdx.x];                     // the table is in XCD order
     const PoolSim &d = sims[tr.slot];
     const long long done = *t_base + t_off - d.t0;
     if (!residual_due(d, done)) return;                       // uniform over the workgroup
@@ -646,7 +684,7 @@ struct vplbm_pool_s {
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph = nullptr;
-    int grid_cap = 0;                     // workgroups per step launch in the captured graph
+    int grid_cap = 0;                     // workgroups per launch in the captured graph
     bool graph_checks = false;            // the graph ends with the residual-check kernels
     int graph_classes = 0;                // storage classes the graph has step kernels for
     PoolSim *d_sims = nullptr;
@@ -731,7 +769,7 @@ int retire(vplbm_pool p, int slot)
     r.obs.status = (d.status & 1u) ? 1 : 0;
     const bool cancelled = r.cancel && done < d.target && !r.obs.status;
     if (done == d.target) {
-        pool_fold_kernel<<<1, 64, 0, p->stream>>>(p->d_sims, slot);
+        pool_fold_kernel<<<kRingWidth, kFoldBlock, 0, p->stream>>>(p->d_sims, slot);
         HIP_TRY(hipGetLastError());
         const char *dev_obs = reinterpret_cast<const char *>(p->d_sims + slot) + offsetof(PoolSim, obs);
         HIP_TRY(hipMemcpyAsync(d.obs, dev_obs, sizeof d.obs, hipMemcpyDeviceToHost, p->stream));
@@ -884,6 +922,8 @@ int ensure_pool_graph(vplbm_pool p)
     }
     int cap = 4096;
     while (cap < p->ntiles) cap *= 2;
+    // every workgroup reads its table entry before it compares its index with the tile count
+    if (cap > p->tile_cap) return fail(VPLBM_EHIP, "tile table (%d entries) shorter than the grid (%d)", p->tile_cap, cap);
     p->grid_cap = cap;
     host_log("pool %p: capture the step graph (%d workgroups per launch, %d steps, residual checks %d)",
         (void *)p, cap, p->cfg.steps_per_launch, (int)checks);
@@ -937,6 +977,17 @@ int ensure_pool_graph(vplbm_pool p)
     return VPLBM_OK;
 }
 
+// Entry b of the device tile table: the tile that workgroup b of a launch over n tiles takes.
+// Workgroups are dealt to the 8 XCDs round-robin; each XCD takes one contiguous range of the
+// tiles (in simulation and tile order), so tiles that share cache lines through the x-shifted
+// pulls stay in one L2.  The kernels then read entry blockIdx.x directly.
+int xcd_entry(int b, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int xcd = b & 7, j = b >> 3;
+    return xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
+}
+
 int upload_tables(vplbm_pool p)
 {
     std::vector<TileRef> tiles;
@@ -970,7 +1021,9 @@ int upload_tables(vplbm_pool p)
     }
     const int n = (int)tiles.size();
     p->ntiles = n;
-    if (n) HIP_TRY(hipMemcpyAsync(p->d_tiles, tiles.data(), sizeof(TileRef) * n, hipMemcpyHostToDevice, p->stream));
+    std::vector<TileRef> order(n);
+    for (int b = 0; b < n; b++) order[b] = tiles[xcd_entry(b, n)];
+    if (n) HIP_TRY(hipMemcpyAsync(p->d_tiles, order.data(), sizeof(TileRef) * n, hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_ntiles, &n, sizeof n, hipMemcpyHostToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_sims, p->h_sims.data(), sizeof(PoolSim) * p->cfg.max_slots, hipMemcpyHostToDevice, p->stream));
     // The host copies above read memory that changes on the next call: finish them.
