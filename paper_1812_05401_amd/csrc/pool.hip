@@ -131,7 +131,7 @@ __device__ __forceinline__ void pool_tile_partials(const PoolSim &d, int tile, d
 template <int S, bool CONV>
 __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long done, int nsteps,
                                           unsigned char *lds, double (*part)[kRingWidth],
-                                          double *outl_lds)
+                                          double *outl_lds, unsigned *status)
 {
     using C = Codec<S>;
     using T = typename C::real;
@@ -139,11 +139,14 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
     constexpr int odirs[3] = {3, 6, 7};           // the directions entering from x = nx
     const Geom &g = d.g;
     const int b = pool_buf(done, d.spl, d.spk);
-    const E *__restrict__ src = static_cast<const E *>(d.buf[b]);
-    E *__restrict__ dst = static_cast<E *>(d.buf[b ^ 1]);
+    // selects rather than indexing: the kernel holds d in registers, not in memory
+    const E *__restrict__ src = static_cast<const E *>(b ? d.buf[1] : d.buf[0]);
+    E *__restrict__ dst = static_cast<E *>(b ? d.buf[0] : d.buf[1]);
     const Outlet none{nullptr, nullptr, 0.0};
-    const Outlet one{CONV ? d.outlet[b] : nullptr, CONV ? d.outlet[b ^ 1] : nullptr, d.ou};
-    const Outlet out1{CONV ? d.outlet[b] : nullptr, nullptr, d.ou};
+    void *const oprev = b ? d.outlet[1] : d.outlet[0];
+    void *const onext = b ? d.outlet[0] : d.outlet[1];
+    const Outlet one{CONV ? oprev : nullptr, CONV ? onext : nullptr, d.ou};
+    const Outlet out1{CONV ? oprev : nullptr, nullptr, d.ou};
     T *outl = reinterpret_cast<T *>(outl_lds);
     const int x0 = (tile % d.ntx) * kPoolTileW, y0 = (tile / d.ntx) * kPoolTileH;
     const int x = x0 + (threadIdx.x % kPoolTileW), y = y0 + (threadIdx.x / kPoolTileW);
@@ -196,7 +199,7 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
             if (CONV && x == g.nx - 1) {
                 // the outlet rule of pull, with the first step's values from LDS
                 const T u = T(d.ou);
-                T *next = static_cast<T *>(d.outlet[b ^ 1]);
+                T *next = static_cast<T *>(onext);
                 for (int k = 0; k < 3; k++) {
                     int pa;
                     const unsigned jn = tile_source(odirs[k], g.nx - 2, y, x0, y0, kPoolEW, g, pa);
@@ -214,7 +217,7 @@ __device__ __forceinline__ void pool_tile(const PoolSim &d, int tile, long long 
             bad |= !(rho > 0.0 && rho < 1e30);
         }
     }
-    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(const_cast<unsigned *>(&d.status), 1u);
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(status, 1u);
     if (done + nsteps == d.target) pool_tile_partials<wave_sum_dpp<T>()>(d, tile, rho, fx, fy, id, part);
 }
 
@@ -309,7 +312,7 @@ __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typenam
 // single-simulation three-step kernel does for its inner tiles.
 template <int S, bool inner>
 __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long done, int k,
-                                           unsigned char *lds, double (*part)[kRingWidth])
+                                           unsigned char *lds, double (*part)[kRingWidth], unsigned *status)
 {
     using C = Codec<S>;
     using T = typename C::real;
@@ -318,8 +321,9 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
     constexpr bool DPP = wave_sum_dpp<T>();
     const Geom &g = d.g;
     const int b = pool_buf(done, d.spl, d.spk);
-    const E *__restrict__ src = static_cast<const E *>(d.buf[b]);
-    E *__restrict__ dst = static_cast<E *>(d.buf[b ^ 1]);
+    // selects rather than indexing: the kernel holds d in registers, not in memory
+    const E *__restrict__ src = static_cast<const E *>(b ? d.buf[1] : d.buf[0]);
+    E *__restrict__ dst = static_cast<E *>(b ? d.buf[0] : d.buf[1]);
     const Outlet none{nullptr, nullptr, 0.0};
     const int x0 = (tile % d.ntx) * TW, y0 = (tile / d.ntx) * TH;
     E *mid = reinterpret_cast<E *>(lds);
@@ -411,7 +415,7 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
             }
         }
     }
-    if (__ballot(bad) && lane == 0) atomicOr(const_cast<unsigned *>(&d.status), 1u);
+    if (__ballot(bad) && lane == 0) atomicOr(status, 1u);
     if (final_step) {
         __syncthreads();
         if (threadIdx.x < kRingWidth) {
@@ -448,10 +452,11 @@ __host__ __device__ inline int pool_spk(int storage, int conv) { return pool_cla
 // single-simulation two-step kernel).
 template <int S>
 __device__ __forceinline__ void pool_tile2(const PoolSim &d, int tile, long long done, int nsteps,
-                                           unsigned char *lds, double (*part)[kRingWidth], double *outl)
+                                           unsigned char *lds, double (*part)[kRingWidth], double *outl,
+                                           unsigned *status)
 {
-    if (d.conv) pool_tile<S, true>(d, tile, done, nsteps, lds, part, outl);
-    else pool_tile<S, false>(d, tile, done, nsteps, lds, part, outl);
+    if (d.conv) pool_tile<S, true>(d, tile, done, nsteps, lds, part, outl, status);
+    else pool_tile<S, false>(d, tile, done, nsteps, lds, part, outl, status);
 }
 
 // Steps t_off .. t_off + nsteps - 1 of the graph replay (nsteps up to the class's steps per
@@ -473,24 +478,28 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     const int n = *ntiles;
     const TileRef tr = tiles[blockIdx.x];                     // the table spans the grid
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
-    const PoolSim &d = sims[tr.slot];
+    // A local copy of the descriptor: its fields are read once into scalar registers (read through
+    // the pointer, they were read again after stores that might alias it: measured 16% of the
+    // kernel's time).  The status flag is written through the pointer.
+    const PoolSim d = sims[tr.slot];
+    unsigned *status = &sims[tr.slot].status;
     const long long done = *t_base + t_off - d.t0;
     if (!d.active || done < 0 || done >= d.target) return;    // uniform over the workgroup
     if (pool_class(d.storage, d.conv) != CLASS) return;
     const int k = d.target - done < nsteps ? int(d.target - done) : nsteps;
     if constexpr (CLASS == 2) {
-        if (pool3_inner(d, tr.tile)) pool_tile3<kF32, true>(d, tr.tile, done, k, lds, part);
-        else pool_tile3<kF32, false>(d, tr.tile, done, k, lds, part);
+        if (pool3_inner(d, tr.tile)) pool_tile3<kF32, true>(d, tr.tile, done, k, lds, part, status);
+        else pool_tile3<kF32, false>(d, tr.tile, done, k, lds, part, status);
     } else if constexpr (CLASS == 1) {
-        if (d.storage == kF64) pool_tile2<kF64>(d, tr.tile, done, k, lds, part, outl);
-        else pool_tile2<kF32D>(d, tr.tile, done, k, lds, part, outl);
+        if (d.storage == kF64) pool_tile2<kF64>(d, tr.tile, done, k, lds, part, outl, status);
+        else pool_tile2<kF32D>(d, tr.tile, done, k, lds, part, outl, status);
     } else {
         switch (d.storage) {
-        case kF32: pool_tile<kF32, true>(d, tr.tile, done, k, lds, part, outl); break;   // outlet only
-        case kF16S: pool_tile2<kF16S>(d, tr.tile, done, k, lds, part, outl); break;
-        case kF16SR: pool_tile2<kF16SR>(d, tr.tile, done, k, lds, part, outl); break;
-        case kBF16SR: pool_tile2<kBF16SR>(d, tr.tile, done, k, lds, part, outl); break;
-        default: pool_tile2<kBF16S>(d, tr.tile, done, k, lds, part, outl); break;
+        case kF32: pool_tile<kF32, true>(d, tr.tile, done, k, lds, part, outl, status); break;   // outlet only
+        case kF16S: pool_tile2<kF16S>(d, tr.tile, done, k, lds, part, outl, status); break;
+        case kF16SR: pool_tile2<kF16SR>(d, tr.tile, done, k, lds, part, outl, status); break;
+        case kBF16SR: pool_tile2<kBF16SR>(d, tr.tile, done, k, lds, part, outl, status); break;
+        default: pool_tile2<kBF16S>(d, tr.tile, done, k, lds, part, outl, status); break;
         }
     }
 }
