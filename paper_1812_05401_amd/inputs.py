@@ -202,13 +202,28 @@ class Request:
     case: Case
 
 
+def column_blockage(bodies, n) -> float:
+    """Largest fraction of a lattice column (x = const) that the bodies' chords cover, overlaps
+    counted twice (an upper bound)."""
+    x = np.arange(n, dtype=np.float64)
+    cover = np.zeros(n)
+    for b in bodies:
+        if b["kind"] == "disk":
+            cover += 2.0 * np.sqrt(np.maximum(b["r"] ** 2 - (x - b["cx"]) ** 2, 0.0))
+        else:
+            cover += np.where(np.abs(x - b["cx"]) <= b["hx"], 2.0 * b["hy"], 0.0)
+    return float(cover.max() / n)
+
+
 def serving_requests(n=256, seed_arrivals=1812, seed_geometry=5401, rate_per_s=1.0,
                      nmin=128, nmax=1024, nstep=32, steps_range=(1000, 20000),
                      re_range=(50.0, 500.0), u=0.05) -> List[Request]:
     """Poisson arrivals of square VP-MRT channel simulations, FP32, 1-8 random disks and
-    rectangles (radius or half-side 8-64), Re 50-500, 1k-20k steps.  Each obstacle lies in
-    x in [N/8, 5N/8], y in [r+2, N-r-3]; draws with more than 30% solid area or tau < 0.51 are
-    redrawn."""
+    rectangles (radius or half-side 8 to min(64, N/8)), Re 50-500, 1k-20k steps.  Each obstacle
+    lies in x in [max(N/8, r+4), 5N/8], y in [r+6, N-r-7]; draws with more than 20% solid area,
+    a column more than 40% blocked (column_blockage) or tau < 0.56 are redrawn.  (With radii up
+    to N/2, obstacles reaching the inlet or two nodes from a wall, crowded columns and tau down
+    to 0.51, 30 of the 256 default requests went unstable.)"""
     ra = np.random.default_rng(seed_arrivals)
     rg = np.random.default_rng(seed_geometry)
     gaps = ra.exponential(1.0 / rate_per_s, n)
@@ -221,18 +236,17 @@ def serving_requests(n=256, seed_arrivals=1812, seed_geometry=5401, rate_per_s=1
             k = int(rg.integers(1, 9))
             bodies, area, rmax = [], 0.0, 0.0
             for _ in range(k):
-                rad = float(rg.uniform(8, 64))
-                rad = min(rad, (N - 6) / 2.0 - 1)
+                rad = float(rg.uniform(8, min(64.0, N / 8.0)))
                 kind = "disk" if rg.random() < 0.5 else "rect"
-                cx = float(rg.uniform(N / 8, 5 * N / 8))
-                cy = float(rg.uniform(rad + 2, N - rad - 3))
+                cx = float(rg.uniform(max(N / 8, rad + 4), 5 * N / 8))
+                cy = float(rg.uniform(rad + 6, N - rad - 7))
                 bodies.append(body(kind, cx, cy, r=rad, hx=rad, hy=rad))
                 area += math.pi * rad * rad if kind == "disk" else 4 * rad * rad
                 rmax = max(rmax, rad)
             re = float(rg.uniform(*re_range))
             tau = tau_from_reynolds(u, 2 * rmax, re)
             steps = int(rg.integers(steps_range[0], steps_range[1] + 1))
-            if area <= 0.3 * N * N and tau >= 0.51:
+            if area <= 0.2 * N * N and tau >= 0.56 and column_blockage(bodies, N) <= 0.4:
                 break
         c = Case(f"req{i}", N, N, collision=MRT, storage="f32", tau=tau, bc=CHANNEL,
                  u_in=(u, 0.0), bodies=bodies, u0=(u, 0.0), steps=steps, diameter=2 * rmax)
