@@ -172,7 +172,7 @@ def time_workload(case, steps, warmup, storage=None, spl=3):
 
 def host_threads():
     """Threads the oracle may use: the processors this process may run on, at most the
-    OMP_NUM_THREADS the environment sets (a GPU machine's CPU share)."""
+    OMP_NUM_THREADS the environment sets (the share of the host's CPUs a job is given)."""
     n = len(os.sched_getaffinity(0))
     env = os.environ.get("OMP_NUM_THREADS", "")
     if env.isdigit() and int(env) > 0:

@@ -20,7 +20,7 @@ def orc_body(b):
 
 def host_threads():
     """Threads the oracle may use here: the processors this process may run on, at most the
-    OMP_NUM_THREADS the environment sets (a GPU machine's CPU share)."""
+    OMP_NUM_THREADS the environment sets (the share of the host's CPUs a job is given)."""
     n = len(os.sched_getaffinity(0))
     env = os.environ.get("OMP_NUM_THREADS", "")
     if env.isdigit() and int(env) > 0:
