@@ -330,3 +330,44 @@ def test_convective_outlet_in_the_pool_matches_the_oracle(gpu):
         sc = force_scale(oo)
         assert np.max(np.abs(obs["fx"] - oo["fx"])) <= 1e-12 * sc
         assert np.max(np.abs(obs["fy"] - oo["fy"])) <= 1e-12 * sc
+
+
+def test_tile_table_growth_mid_run(gpu):
+    """A request runs alone (1184 tiles), then three more join (4736 tiles: the device tile table
+    outgrows its first 4096 entries and the graph is captured again); a 128² request joins
+    last.  Every request's fields are bitwise those of the single-simulation path, binary32
+    (three steps per launch) and FP64 (two) alike."""
+    B = gpu
+    cases = []
+    for k, st in enumerate(("f32", "f32", "f64", "f32")):
+        c = I.Case(f"big{k}", 1024, 1024, collision="mrt" if k % 2 == 0 else "srt", storage=st,
+                   tau=0.6 + 0.05 * k, bc=I.CHANNEL, u_in=(0.04, 0.0), u0=(0.04, 0.0),
+                   bodies=[I.body("disk", 300 + 40 * k, 511.5, r=40), I.body("rect", 600, 300, hx=20, hy=30)],
+                   steps=97 + 10 * k)
+        cases.append(c)
+    small = small_requests(seed=29, n=1, storage="f32")[0]
+    small.steps = 131
+    pool = B.Pool(4 << 30, max_slots=8, steps_per_launch=16)
+    ids = [pool.submit(cases[0], cases[0].steps, keep_fields=True)]
+    pool.advance()
+    pool.advance()                                       # the first request runs alone
+    ids += [pool.submit(c, c.steps, keep_fields=True) for c in cases[1:]]
+    pool.advance()
+    ids.append(pool.submit(small, small.steps, keep_fields=True))
+    res = {}
+    while len(res) < len(ids):
+        pool.advance()
+        for k, rid in enumerate(ids):
+            if k not in res and pool.status(rid)[0] >= 2:
+                res[k] = pool.result(rid, fields=True)
+    pool.close()
+    for k, c in enumerate(cases + [small]):
+        obs, fields = res[k]
+        assert obs["status"] == 0 and obs["step"] == c.steps - 1
+        s = B.Simulation(c, stream=None)
+        s.step(c.steps)
+        so, *sfields = s.observables(fields=True)
+        s.close()
+        for a, b in zip(fields, sfields):
+            assert np.array_equal(a, b), f"{c.name}/{c.storage}"
+        assert abs(obs["mass"] - so["mass"]) <= 1e-13 * so["mass"]
