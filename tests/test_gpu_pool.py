@@ -371,3 +371,37 @@ def test_tile_table_growth_mid_run(gpu):
         for a, b in zip(fields, sfields):
             assert np.array_equal(a, b), f"{c.name}/{c.storage}"
         assert abs(obs["mass"] - so["mass"]) <= 1e-13 * so["mass"]
+
+
+def test_many_tiny_lattices(gpu):
+    """300 lattices from 3 x 3 to 40 x 40 in one pool (ragged tiles, periodic edges narrower
+    than the three-step kernel's two-node halo, every storage format, both collisions, 300
+    slots): each is bitwise the single-simulation run of as many steps."""
+    B = gpu
+    r = np.random.default_rng(31)
+    storages = ("f32", "f64", "f16s", "bf16s", "f32d", "f16sr", "bf16sr")
+    cases = []
+    for k in range(300):
+        nx, ny = int(r.integers(3, 41)), int(r.integers(3, 41))
+        periodic = k % 2 == 0
+        bc = I.ALL_PERIODIC if periodic else I.CHANNEL
+        u = (0.02, 0.01) if periodic else (0.03, 0.0)
+        bodies = []
+        if min(nx, ny) >= 12 and k % 3 == 0:
+            bodies = [I.body("disk", nx / 2, ny / 2, r=min(nx, ny) / 5, omega=0.002)]
+        cases.append(I.Case(f"tiny{k}", nx, ny, collision="mrt" if k % 4 < 2 else "srt",
+                            storage=storages[k % len(storages)], tau=0.6 + 0.3 * r.random(), bc=bc,
+                            u_in=(0.03, 0.0) if not periodic else (0.0, 0.0), u0=u, bodies=bodies,
+                            steps=int(r.integers(1, 60))))
+    res, max_running = run(B.Pool, cases, 1 << 30, slots=300, spl=7)
+    assert max_running == 300
+    for k, c in enumerate(cases):
+        obs, fields = res[k]
+        assert obs["status"] == 0 and obs["step"] == c.steps - 1
+        s = B.Simulation(c, stream=None)
+        s.step(c.steps)
+        so, *sfields = s.observables(fields=True)
+        s.close()
+        for a, b in zip(fields, sfields):
+            assert np.array_equal(a, b), f"{c.name} {c.nx}x{c.ny} {c.storage}, {c.steps} steps"
+        assert abs(obs["mass"] - so["mass"]) <= 1e-12 * abs(so["mass"])
