@@ -264,13 +264,16 @@ def serving_leg(n_requests, loads, budget_bytes, fifo_loads):
         return [dataclasses.replace(r, arrival=r.arrival / rate) for r in base]
 
     out["max_resident_nodes"] = serve.DEFAULT_RESIDENT_NODES
+    out["steps_per_replay"] = serve.SERVING_REPLAY_STEPS
     for load in loads:
-        stats, _ = serve.run_pool(at_load(load), budget_bytes, max_slots=128, steps_per_launch=64)
+        stats, _ = serve.run_pool(at_load(load), budget_bytes, max_slots=128,
+                                  steps_per_launch=serve.SERVING_REPLAY_STEPS)
         out["runs"][f"pool_load_{load}"] = stats
         print(f"# serving pool load {load}: p50 {stats['p50_s']:.2f} s p99 {stats['p99_s']:.2f} s "
               f"{stats['aggregate_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     # the same pool without the admission cap, at the highest load
-    stats, _ = serve.run_pool(at_load(max(loads)), budget_bytes, max_slots=128, steps_per_launch=64,
+    stats, _ = serve.run_pool(at_load(max(loads)), budget_bytes, max_slots=128,
+                              steps_per_launch=serve.SERVING_REPLAY_STEPS,
                               max_resident_nodes=0)
     out["runs"][f"pool_uncapped_load_{max(loads)}"] = stats
     print(f"# serving pool (no admission cap) load {max(loads)}: p50 {stats['p50_s']:.2f} s "

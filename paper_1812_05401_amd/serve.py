@@ -16,6 +16,12 @@ from . import binding as B
 # (python -m paper_1812_05401_amd.serve --cap-sweep).
 DEFAULT_RESIDENT_NODES = 256 * 4 * 512 * 4
 
+# Steps per graph replay of the pool for serving: each replay ends with a host round trip
+# (retire, admit) of about 70 us in which the GPU idles.  On the 256-request stream, p50 / p99 at
+# 1.2x capacity: 0.21 / 0.65 s with 32 steps, 0.19 / 0.59 s with 64, 0.17 / 0.55 s with 128 and
+# 256, 0.18 / 0.56 s with 512 (coarser admission).
+SERVING_REPLAY_STEPS = 128
+
 
 def _percentiles(ttr):
     a = np.asarray(ttr)
@@ -23,7 +29,8 @@ def _percentiles(ttr):
             "mean_s": float(a.mean()), "max_s": float(a.max())}
 
 
-def run_pool(requests, budget_bytes, max_slots=128, steps_per_launch=64, stream=None,
+def run_pool(requests, budget_bytes, max_slots=128, steps_per_launch=SERVING_REPLAY_STEPS,
+             stream=None,
              keep_fields=False, on_result=None, poll_sleep_s=0.0005,
              max_resident_nodes=DEFAULT_RESIDENT_NODES):
     """Replay `requests` through a Pool.  Returns summary statistics (with the number of requests
@@ -117,7 +124,7 @@ def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4
     for load in loads:
         reqs = [dataclasses.replace(r, arrival=r.arrival / (load * cap_rps)) for r in base]
         for cap in caps:
-            st, _ = run_pool(reqs, budget_bytes, max_slots=128, steps_per_launch=64,
+            st, _ = run_pool(reqs, budget_bytes, max_slots=128, steps_per_launch=SERVING_REPLAY_STEPS,
                              max_resident_nodes=cap)
             print(f"load {load} cap {cap:>8d}: p50 {st['p50_s']:.3f} p99 {st['p99_s']:.3f} "
                   f"mean {st['mean_s']:.3f} max {st['max_s']:.3f} GLUPS {st['aggregate_mlups'] / 1e3:.1f} "
@@ -129,7 +136,8 @@ def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4
                   f"failed {st['failed']}", flush=True)
 
 
-def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30, steps_per_launch=64):
+def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30,
+                steps_per_launch=SERVING_REPLAY_STEPS):
     """Throughput of a fixed batch: n square requests of one grid (the serving stream's geometry
     draws, all `steps` long, in `storage`) submitted at once to a pool without an admission cap,
     timed after the first graph replay (which admits them);
