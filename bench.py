@@ -7,9 +7,10 @@ moments, penalization, collision, store, and the FP64 mass/force reductions.  Th
 workload is the 8192 x 2048 transversely oscillating cylinder (VP-MRT, FP32 storage, Zou-He
 inlet, outflow, free-slip walls, disk D = 96, Re = 300, mask and solid velocity rebuilt on the
 device every step).  Its two population buffers (1.2 GB) far exceed the 256 MB Infinity Cache, so
-the step streams from HBM and the line's `roofline` is an HBM figure.  The library runs two steps
-per launch (the intermediate step kept in LDS); `one_step_per_launch` times the same workload with
-one step per launch, the memory-bound kernel.  Beside it the line carries `cache_resident` (the
+the step streams from HBM and the line's `roofline` is an HBM figure.  The library runs three
+steps per launch (the intermediate steps kept in LDS); `two_steps_per_launch` and
+`one_step_per_launch` time the same workload with two steps per launch and with one, the
+memory-bound kernel.  Beside it the line carries `cache_resident` (the
 2048 x 512 cylinder wake, whose 75 MB of buffers fit in the cache: MLUPS only),
 `taylor_couette_128` (the 128 x 128 FP64 case, launch-bound: MLUPS only), `reduced_precision`
 (the 8192 x 2048 cylinder in every storage format), `paper_cylinder_re500` (the paper's
@@ -89,7 +90,7 @@ def measured_traffic(workload, storage, steps_per_launch=1):
 def time_workload(case, steps, warmup, storage=None, spl=3):
     """Time `steps` steps of `case` after `warmup`, with at most `spl` steps per launch: 1 creates
     the simulation with VPLBM_TWO_STEP=0, 2 with VPLBM_THREE_STEP=0; the library takes as many as
-    the case allows (three for binary32 storage without a convective outlet, else two)."""
+    the case allows (three for binary32 storage, else two)."""
     import torch
     from paper_1812_05401_amd import binding as B
     if storage:
@@ -520,11 +521,11 @@ def main():
         line["reduced_precision"] = {"workload": "cylinder_wake_8192x2048", **red}
         # the paper's own Re = 500 cylinder (6048 x 2016, SRT, convective outlet), FP32
         pcr = {}
-        for two in (True, False):
-            r = time_workload(I.paper_cylinder_re500("f32"), 400, 40, spl=2 if two else 1)
-            pcr["two_steps_per_launch" if two else "one_step_per_launch"] = {
-                k: r[k] for k in ("mlups", "ms_per_step", "steps_per_launch", "roofline")}
-            print(f"# paper_cylinder_re500 ({'two' if two else 'one'} per launch): {r['mlups']:.0f} MLUPS",
+        for spl, key in ((3, "three_steps_per_launch"), (2, "two_steps_per_launch"),
+                         (1, "one_step_per_launch")):
+            r = time_workload(I.paper_cylinder_re500("f32"), 402, 42, spl=spl)
+            pcr[key] = {k: r[k] for k in ("mlups", "ms_per_step", "steps_per_launch", "roofline")}
+            print(f"# paper_cylinder_re500 ({spl} per launch): {r['mlups']:.0f} MLUPS",
                   file=sys.stderr, flush=True)
         line["paper_cylinder_re500"] = {"workload": "paper_cylinder_re500", "storage": "f32", **pcr}
         # FP32 square channels from cache-resident to far beyond the 256 MB Infinity Cache

@@ -199,9 +199,9 @@ int vplbm_momentum_exchange_noalloc(vplbm_sim s, double *out);
 int vplbm_steps_done(vplbm_sim s, int64_t *steps);
 int vplbm_stream(vplbm_sim s, void **stream);
 
-/* Lattice updates per kernel launch for this simulation: 3 for binary32 storage without a
-   convective outlet (the two intermediate steps kept on chip, 64 x 14 tiles), 2 for the other cases
-   (pairs of steps, the intermediate one kept on chip), 1 when the environment variable
+/* Lattice updates per kernel launch for this simulation: 3 for binary32 storage (the two
+   intermediate steps kept on chip, 64 x 14 tiles; the convective outlet included), 2 for the
+   other formats (pairs of steps, the intermediate one kept on chip), 1 when the environment variable
    VPLBM_TWO_STEP=0 was set at create; VPLBM_THREE_STEP=0 at create caps it at 2.  Moving bodies
    get a mask of their own for each intermediate step.  What remains of a call after its full
    launches takes launches of one or two steps.  Every launch shape gives bitwise the same

@@ -357,7 +357,7 @@ class Simulation:
 
     @property
     def steps_per_launch(self):
-        """3 for binary32 storage without a convective outlet, else 2 (pairs of steps per launch);
+        """3 for binary32 storage, else 2 (pairs of steps per launch);
         VPLBM_THREE_STEP=0 caps it at 2 and VPLBM_TWO_STEP=0 at 1."""
         return vplbm_steps_per_launch(self.h)
 

@@ -290,15 +290,19 @@ __global__ __launch_bounds__(kBlock2) void step2_kernel(StepArgs a)
 // of three one-step launches, with one read and one write of the planes per three updates.  A halo
 // position across a periodic edge holds the wrapped node; one beyond a non-periodic edge or a
 // ragged tile is skipped (no later pull reads it).  The phases take the masks and body states of
-// their own steps (a.mask, a.mask2, a.mask3).  There is no convective outlet here: the host uses
-// the two-step kernel for it.  Tiles: 64 x 14 for binary32 (46 KB of LDS, three workgroups per
+// their own steps (a.mask, a.mask2, a.mask3).  CONV (an instantiation of its own): the lattice
+// has a convective outlet; phase 1 reads the previous launch's records from global memory and
+// keeps the values it records at x = nx - 1 for the tile's rows and a one-row halo in LDS, phase 2
+// applies the outlet rule with them and keeps its own for the tile's rows, and phase 3 applies it
+// with those and records its values in global memory for the next launch.  Only tiles that reach
+// the last column take this code.  Tiles: 64 x 14 for binary32 (46 KB of LDS, three workgroups per
 // CU; the phases cover 1224, 1056 and 896 nodes, 1.18 computed per update).  Measured at
 // 8192 x 2048: 111 us per step, against 113 for 64 x 12, 116 for 64 x 16, 118 for 32 x 24, 123 for
 // 128 x 6 and 64 x 10, 127 for 128 x 10, 137 for 128 x 8 (two workgroups per CU) and 151 for
 // 256 x 4: the VALUs bound this kernel, and taller tiles recompute less halo.  Inner tiles load and
 // the last phase stores through buffer resources (pull_interior_buf, store_node_buf), which keep
 // the plane offsets out of the vector ALUs.
-template <int S, int TW, int TH, bool NT>
+template <int S, int TW, int TH, bool NT, bool CONV>
 __global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
 {
     using C = Codec<S>;
@@ -314,6 +318,11 @@ __global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
     constexpr bool DPP = wave_sum_dpp<T>();
     __shared__ E mid[9 * EN];                           // steps t, then t + 1, on the tile
     __shared__ double wave_acc[3][NW][kRingWidth];      // per-wave partials of the three steps
+    // convective outlet: the values steps t and t + 1 record at x = nx - 1, rows y0 - 1 ..
+    // y0 + TH (unwrapped) and y0 .. y0 + TH - 1
+    __shared__ T outl1[CONV ? 3 : 1][TH + 2];
+    __shared__ T outl2[CONV ? 3 : 1][TH];
+    constexpr int odirs[3] = {3, 6, 7};                 // the directions entering from x = nx
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long long t = *a.t_base + a.t_off;
     const Geom &g = a.g;
@@ -331,6 +340,7 @@ __global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
     const __amdgpu_buffer_rsrc_t rsrc = buffer_over(const_cast<void *>(a.src), bytes);
     const __amdgpu_buffer_rsrc_t rdst = buffer_over(a.dst, bytes);
     const Outlet none{nullptr, nullptr, 0.0};
+    const Outlet out1{a.outlet.prev, nullptr, a.outlet.u};   // step t reads the outlet, records here
     bool bad = false;
     double mass = 0.0;
     // A tile three or more nodes from every edge: every node of every phase pulls by plain shifts
@@ -368,7 +378,9 @@ __global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
             if constexpr (MF) id = *at(a.mask, unsigned(y * g.pitch + x));
             T f[9];
             if (inner) pull_interior_buf<S>(rsrc, g.plane, g.pitch, unsigned(y * g.pitch + x), f);
-            else pull<S>(src, x, y, g, none, f);
+            else pull<S>(src, x, y, g, CONV ? out1 : none, f);
+            if (CONV && !inner && x == g.nx - 1 && uy >= y0 - 1 && uy <= y0 + TH)
+                for (int q = 0; q < 3; q++) outl1[q][uy - y0 + 1] = f[odirs[q]];
             const Macro<T> m = MF ? relax_node_id(f, id, a.bodies, g, a.p, x, y)
                                   : relax_node(f, a.mask, a.bodies, g, a.p, x, y, id);
             store_node<S>(mid, EN, unsigned(e), f, unsigned(y * g.pitch + x), (unsigned)t);
@@ -410,6 +422,18 @@ __global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
             if constexpr (MF) id = *at(a.mask2, node[it]);
             if (inner) pull_tile_shifts<S, 2>(mid, EN, EW, ux, uy, x0, y0, res[it]);
             else pull_tile<S, 2>(mid, EN, EW, ux, uy, x0, y0, g, res[it]);
+            if (CONV && !inner && x == g.nx - 1) {
+                // the outlet rule of pull, with step t's records and neighbours from LDS
+                const T u = T(a.outlet.u);
+                for (int q = 0; q < 3; q++) {
+                    int pa;
+                    const unsigned jn = tile_source<2>(odirs[q], g.nx - 2, uy, x0, y0, EW, g, pa);
+                    const T nb = C::load(mid + pa * EN, jn, weight<T>(odirs[q]));
+                    res[it][odirs[q]] = (outl1[q][uy - y0 + 1] + u * nb) / (T(1) + u);
+                }
+                if (uy >= y0 && uy < y0 + TH)
+                    for (int q = 0; q < 3; q++) outl2[q][uy - y0] = res[it][odirs[q]];
+            }
             const Macro<T> m = MF ? relax_node_id(res[it], id, a.bodies2, g, a.p, x, y)
                                   : relax_node(res[it], a.mask2, a.bodies2, g, a.p, x, y, id);
             if (in_tile(ux, uy)) {
@@ -448,6 +472,18 @@ __global__ __launch_bounds__(kBlock2) void step3_kernel(StepArgs a)
             T f[9];
             if (inner) pull_tile_shifts<S, 2>(mid, EN, EW, x, y, x0, y0, f);
             else pull_tile<S, 2>(mid, EN, EW, x, y, x0, y0, g, f);
+            if (CONV && !inner && x == g.nx - 1) {
+                // the outlet rule with step t + 1's records; this step's go to global memory
+                const T u = T(a.outlet.u);
+                T *next = static_cast<T *>(a.outlet.next);
+                for (int q = 0; q < 3; q++) {
+                    int pa;
+                    const unsigned jn = tile_source<2>(odirs[q], g.nx - 2, y, x0, y0, EW, g, pa);
+                    const T nb = C::load(mid + pa * EN, jn, weight<T>(odirs[q]));
+                    f[odirs[q]] = (outl2[q][y - y0] + u * nb) / (T(1) + u);
+                }
+                for (int q = 0; q < 3; q++) next[q * g.ny + y] = f[odirs[q]];
+            }
             const Macro<T> m = MF ? relax_node_id(f, id, a.bodies3, g, a.p, x, y)
                                   : relax_node(f, a.mask3, a.bodies3, g, a.p, x, y, id);
             store_node_buf<S, NT>(rdst, g.plane, y * g.pitch + x, f);
@@ -545,10 +581,15 @@ bool step3_supported(int storage) { return storage == kF32; }
 hipError_t launch_step3(int storage, const StepArgs &a, hipStream_t st)
 {
     constexpr int TW = 64, TH = 14;
-    if (storage != kF32 || a.outlet.prev) return hipErrorInvalidValue;
+    if (storage != kF32) return hipErrorInvalidValue;
     const dim3 grid(((a.g.nx + TW - 1) / TW) * ((a.g.ny + TH - 1) / TH)), block(kBlock2);
-    if (a.nt_store) step3_kernel<kF32, TW, TH, true><<<grid, block, 0, st>>>(a);
-    else step3_kernel<kF32, TW, TH, false><<<grid, block, 0, st>>>(a);
+    if (a.outlet.prev) {   // convective outlet: an instantiation of its own
+        if (a.nt_store) step3_kernel<kF32, TW, TH, true, true><<<grid, block, 0, st>>>(a);
+        else step3_kernel<kF32, TW, TH, false, true><<<grid, block, 0, st>>>(a);
+    } else {
+        if (a.nt_store) step3_kernel<kF32, TW, TH, true, false><<<grid, block, 0, st>>>(a);
+        else step3_kernel<kF32, TW, TH, false, false><<<grid, block, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 

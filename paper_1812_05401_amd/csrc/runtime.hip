@@ -238,12 +238,11 @@ bool two_step_ok(vplbm_sim s)
     return s->two_step && (!s->moving || s->mask_alt);
 }
 
-// Three steps per launch: binary32 storage without a convective outlet, planes below 4 GB (the
-// kernel stores through a 32-bit buffer resource); moving bodies take masks of their own for the
-// first two steps.
+// Three steps per launch: binary32 storage, planes below 4 GB (the kernel stores through a 32-bit
+// buffer resource); moving bodies take masks of their own for the first two steps.
 bool three_step_ok(vplbm_sim s)
 {
-    return s->three_step && two_step_ok(s) && step3_supported(s->storage) && !s->outlet[0] &&
+    return s->three_step && two_step_ok(s) && step3_supported(s->storage) &&
            s->buf_bytes <= 0xFFFFFFFFu && (!s->moving || s->mask_alt2);
 }
 
@@ -597,7 +596,7 @@ int vplbm_set_mask(vplbm_sim s, const uint8_t *body_id, const vplbm_body *bodies
         s->mask_alt = nullptr;
         return fail(VPLBM_ENOMEM, "cannot allocate the second mask (%zu bytes)", (size_t)g.pitch * g.ny);
     }
-    const bool third = moving && s->three_step && step3_supported(s->storage) && !s->outlet[0] &&
+    const bool third = moving && s->three_step && step3_supported(s->storage) &&
                        s->buf_bytes <= 0xFFFFFFFFu;
     if (third && !s->mask_alt2 && hipMalloc(&s->mask_alt2, (size_t)g.pitch * g.ny) != hipSuccess) {
         (void)hipGetLastError();

@@ -2,8 +2,8 @@
 launch.  The populations must be bitwise the same in every storage format and edge combination,
 over graph replays, odd remainders and restarts.  The per-step ring values (mass, body forces) are
 FP64 sums over different tilings, so they agree up to summation order (1e-13 relative).  Three
-steps per launch exist for binary32 storage without a convective outlet; elsewhere a request for
-them gets two."""
+steps per launch exist for binary32 storage (the convective outlet included); elsewhere a request
+for them gets two."""
 import contextlib
 import os
 
@@ -39,7 +39,7 @@ def env(**kw):
 def expected_spl(case, storage, spl):
     """Steps per launch the library takes when asked for at most spl (True: 2, False: 1)."""
     spl = int(spl) + 1 if isinstance(spl, bool) else spl
-    if spl == 3 and (storage != "f32" or case.bc[1] == I.CONVECTIVE):
+    if spl == 3 and storage != "f32":
         return 2
     return spl
 
@@ -100,7 +100,7 @@ def test_two_step_bitwise_equals_one_step(gpu, capfd, spec, storage):
 
 @pytest.mark.parametrize("spec", TWO, ids=[c[0] for c in TWO])
 def test_three_step_bitwise_equals_one_step(gpu, capfd, spec):
-    """Binary32 storage with three steps per launch (two with the convective outlet): 101 steps
+    """Binary32 storage with three steps per launch (the convective outlet included): 101 steps
     (three 32-step graph replays of ten three-step launches and a two-step one each, then a
     three-step and a two-step launch), then 1, 3, 2 and 5 more: bitwise the same populations as
     one step per launch."""
@@ -160,7 +160,7 @@ def test_two_step_full_size(gpu, nx, ny, storage, steps):
     """The benchmark lattices in the launch configuration the benchmark times (graph replays of
     three-step launches for binary32, two-step launches otherwise, non-temporal stores on the large
     lattice), a ragged lattice large enough for the tall 2-byte tiles, and the paper's Re = 500
-    cylinder with its convective outlet (two steps per launch)."""
+    cylinder with its convective outlet (three steps per launch)."""
     if (nx, ny) == (6048, 2016):
         case = I.paper_cylinder_re500(storage=storage)
     else:
