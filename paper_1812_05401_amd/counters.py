@@ -50,8 +50,10 @@ def bytes_per_update(storage):
 
 
 def kernel_short_name(name):
-    """A kernel's name without its argument list and a leading return type."""
-    n = re.sub(r"\(.*", "", name).strip()
+    """A kernel's name without its argument list and a leading return type (an anonymous
+    namespace is kept as `(anonymous namespace)::`)."""
+    n = name.replace("(anonymous namespace)::", "\0")
+    n = re.sub(r"\(.*", "", n).strip().replace("\0", "(anonymous namespace)::")
     return n[5:] if n.startswith("void ") else n
 
 
