@@ -224,7 +224,7 @@ int vplbm_bytes_per_update(int32_t storage, int64_t *bytes);
  * resident: fields are bitwise identical alone and in a mix, and the final mass and body forces
  * are summed per tile in a fixed order.  Bodies must be static (no prescribed motion) and are
  * rasterized on the device.  Every edge condition of a single simulation is accepted, the
- * convective outlet included (its requests take two steps per launch whatever their storage).
+ * convective outlet included (its requests take the launches of their storage format).
  */
 typedef struct vplbm_pool_s *vplbm_pool;
 

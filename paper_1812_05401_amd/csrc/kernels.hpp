@@ -61,10 +61,10 @@ TileShape tile_shape(int nx, int ny, int elem_bytes);
 
 hipError_t launch_step(int storage, const StepArgs &a, hipStream_t st);
 // Steps *t_base + t_off and the one after in one launch, from a.src into a.dst; the second step
-// takes its mask and body states from a.mask2 / a.bodies2 (no convective outlet).
+// takes its mask and body states from a.mask2 / a.bodies2 (the convective outlet included).
 hipError_t launch_step2(int storage, const StepArgs &a, hipStream_t st);
-// Steps *t_base + t_off .. + 2 in one launch (binary32 storage without a convective outlet); the
-// second and third steps take a.mask2 / a.bodies2 and a.mask3 / a.bodies3.
+// Steps *t_base + t_off .. + 2 in one launch (binary32 storage, the convective outlet included);
+// the second and third steps take a.mask2 / a.bodies2 and a.mask3 / a.bodies3.
 bool step3_supported(int storage);
 hipError_t launch_step3(int storage, const StepArgs &a, hipStream_t st);
 

@@ -269,17 +269,22 @@ __device__ __forceinline__ void pool_store_buf(__amdgpu_buffer_rsrc_t r, unsigne
 
 // First phase of a multi-step launch on a 64 x kPool3H tile: step `step` on the tile and a halo
 // of H nodes, from the planes in global memory into the LDS tile, whose slots are laid out with a
-// two-node halo (kPool3EW per row) whatever H is.  Returns whether an own node went bad.
-template <int S, int H, bool inner>
+// two-node halo (kPool3EW per row) whatever H is.  Returns whether an own node went bad.  CONV:
+// the convective outlet reads the previous records `prev` and the values this step records at
+// x = nx - 1 go to rec1 for rows y0 - 1 .. y0 + kPool3H (3 x (kPool3H + 2), unwrapped rows).
+template <int S, int H, bool inner, bool CONV = false>
 __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typename Codec<S>::elem *src,
                                                  __amdgpu_buffer_rsrc_t rsrc,
                                                  typename Codec<S>::elem *mid, int x0, int y0,
-                                                 unsigned step)
+                                                 unsigned step, void *prev = nullptr,
+                                                 typename Codec<S>::real *rec1 = nullptr)
 {
     using T = typename Codec<S>::real;
     constexpr int W1 = kPoolTileW + 2 * H, N1 = W1 * (kPool3H + 2 * H);
+    constexpr int odirs[3] = {3, 6, 7};           // the directions entering from x = nx
     const Geom &g = d.g;
     const Outlet none{nullptr, nullptr, 0.0};
+    const Outlet out1{prev, nullptr, d.ou};
     bool bad = false;
     for (int e = threadIdx.x; e < N1; e += kBlock2) {
         const int ux = x0 + e % W1 - H, uy = y0 + e / W1 - H;
@@ -288,7 +293,9 @@ __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typenam
         T f[9];
         int id;
         if constexpr (inner) pool_pull_buf(rsrc, g.plane, g.pitch, unsigned(y * g.pitch + x), f);
-        else pull<S>(src, x, y, g, none, f);
+        else pull<S>(src, x, y, g, CONV ? out1 : none, f);
+        if (CONV && x == g.nx - 1 && uy >= y0 - 1 && uy <= y0 + kPool3H)
+            for (int q = 0; q < 3; q++) rec1[q * (kPool3H + 2) + (uy - y0 + 1)] = f[odirs[q]];
         const auto m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
         store_node<S>(mid, kPool3EN, unsigned((uy - y0 + 2) * kPool3EW + (ux - x0 + 2)), f,
                       unsigned(y * g.pitch + x), step);
@@ -309,10 +316,13 @@ __device__ __forceinline__ bool pool_first_phase(const PoolSim &d, const typenam
 // added in order, rows in order).  inner: the tile lies three or more nodes from every edge of a
 // simulation whose planes span less than 4 GB (pool3_inner); then every phase pulls by plain
 // shifts, the first through a buffer resource, and the last stores through one, as the
-// single-simulation three-step kernel does for its inner tiles.
-template <int S, bool inner>
+// single-simulation three-step kernel does for its inner tiles.  CONV (edge tiles only): the
+// convective outlet, its recorded values passed from phase to phase in LDS (outl_lds) as in the
+// single-simulation three-step kernel, the last phase writing them for the next launch.
+template <int S, bool inner, bool CONV>
 __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long done, int k,
-                                           unsigned char *lds, double (*part)[kRingWidth], unsigned *status)
+                                           unsigned char *lds, double (*part)[kRingWidth],
+                                           double *outl_lds, unsigned *status)
 {
     using C = Codec<S>;
     using T = typename C::real;
@@ -325,6 +335,11 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
     const E *__restrict__ src = static_cast<const E *>(b ? d.buf[1] : d.buf[0]);
     E *__restrict__ dst = static_cast<E *>(b ? d.buf[0] : d.buf[1]);
     const Outlet none{nullptr, nullptr, 0.0};
+    void *const oprev = b ? d.outlet[1] : d.outlet[0];
+    void *const onext = b ? d.outlet[0] : d.outlet[1];
+    constexpr int odirs[3] = {3, 6, 7};           // the directions entering from x = nx
+    T *rec1 = reinterpret_cast<T *>(outl_lds);     // first phase's records, rows y0 - 1 .. y0 + TH
+    T *rec2 = rec1 + 3 * (TH + 2);                 // middle phase's records, rows y0 .. y0 + TH - 1
     const int x0 = (tile % d.ntx) * TW, y0 = (tile / d.ntx) * TH;
     E *mid = reinterpret_cast<E *>(lds);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -335,7 +350,7 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
     const __amdgpu_buffer_rsrc_t rdst = buffer_over(dst, unsigned(pbytes));
     bool bad = false;
     if (k == 3) {
-        bad |= pool_first_phase<S, 2, inner>(d, src, rsrc, mid, x0, y0, (unsigned)done);
+        bad |= pool_first_phase<S, 2, inner, CONV>(d, src, rsrc, mid, x0, y0, (unsigned)done, oprev, rec1);
         __syncthreads();
         constexpr int MW = TW + 2, MN = MW * (TH + 2), R2 = (MN + kBlock2 - 1) / kBlock2;
         T res[R2][9];
@@ -352,6 +367,18 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
                 int id;
                 if constexpr (inner) pull_tile_shifts<S, 2>(mid, EN, EW, ux, uy, x0, y0, res[it]);
                 else pull_tile<S, 2>(mid, EN, EW, ux, uy, x0, y0, g, res[it]);
+                if (CONV && x == g.nx - 1) {
+                    // the outlet rule of pull, with the first phase's records and neighbours
+                    const T u = T(d.ou);
+                    for (int q = 0; q < 3; q++) {
+                        int pa;
+                        const unsigned jn = tile_source<2>(odirs[q], g.nx - 2, uy, x0, y0, EW, g, pa);
+                        const T nb = C::load(mid + pa * EN, jn, weight<T>(odirs[q]));
+                        res[it][odirs[q]] = (rec1[q * (TH + 2) + (uy - y0 + 1)] + u * nb) / (T(1) + u);
+                    }
+                    if (uy >= y0 && uy < y0 + TH)
+                        for (int q = 0; q < 3; q++) rec2[q * TH + (uy - y0)] = res[it][odirs[q]];
+                }
                 const auto m = relax_node(res[it], d.mask, d.bodies, g, d.p, x, y, id);
                 slot[it] = (j / MW + 1) * EW + j % MW + 1;
                 node[it] = unsigned(y * g.pitch + x);
@@ -367,7 +394,7 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
             if (slot[it] >= 0) store_node<S>(mid, EN, unsigned(slot[it]), res[it], node[it], (unsigned)(done + 1));
         __syncthreads();
     } else if (k == 2) {
-        bad |= pool_first_phase<S, 1, inner>(d, src, rsrc, mid, x0, y0, (unsigned)done);
+        bad |= pool_first_phase<S, 1, inner, CONV>(d, src, rsrc, mid, x0, y0, (unsigned)done, oprev, rec1);
         __syncthreads();
     }
     constexpr int R3 = (TW * TH + kBlock2 - 1) / kBlock2;
@@ -380,11 +407,26 @@ __device__ __forceinline__ void pool_tile3(const PoolSim &d, int tile, long long
         if ((j < TW * TH) & (x < g.nx) & (y < g.ny)) {
             Macro<T> m;
             if (k == 1) {
-                m = update_node<S>(src, dst, d.mask, d.bodies, g, none, d.p, x, y, id, (unsigned)done);
+                const Outlet one{oprev, onext, d.ou};
+                m = update_node<S>(src, dst, d.mask, d.bodies, g, CONV ? one : none, d.p, x, y, id,
+                                   (unsigned)done);
             } else {
                 T f[9];
                 if constexpr (inner) pull_tile_shifts<S, 2>(mid, EN, EW, x, y, x0, y0, f);
                 else pull_tile<S, 2>(mid, EN, EW, x, y, x0, y0, g, f);
+                if (CONV && x == g.nx - 1) {
+                    // the outlet rule with the previous phase's records; this step's go to memory
+                    const T u = T(d.ou);
+                    T *next = static_cast<T *>(onext);
+                    for (int q = 0; q < 3; q++) {
+                        int pa;
+                        const unsigned jn = tile_source<2>(odirs[q], g.nx - 2, y, x0, y0, EW, g, pa);
+                        const T nb = C::load(mid + pa * EN, jn, weight<T>(odirs[q]));
+                        const T pr = k == 3 ? rec2[q * TH + (y - y0)] : rec1[q * (TH + 2) + (y - y0 + 1)];
+                        f[odirs[q]] = (pr + u * nb) / (T(1) + u);
+                    }
+                    for (int q = 0; q < 3; q++) next[q * g.ny + y] = f[odirs[q]];
+                }
                 m = relax_node(f, d.mask, d.bodies, g, d.p, x, y, id);
                 const unsigned i = y * g.pitch + x;
                 if constexpr (!inner) store_node<S>(dst, g.plane, i, f, i, (unsigned)(done + k - 1));
@@ -441,7 +483,7 @@ __device__ __forceinline__ bool pool3_inner(const PoolSim &d, int tile)
 // and LDS: measured 4 waves per SIMD with one kernel for all.
 __host__ __device__ inline int pool_class(int storage, int conv)
 {
-    return storage == kF64 || storage == kF32D ? 1 : (storage == kF32 && !conv ? 2 : 0);
+    return storage == kF64 || storage == kF32D ? 1 : (storage == kF32 ? 2 : 0);
 }
 
 // Tile height and steps per kernel launch of a storage format's class.
@@ -474,7 +516,8 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     // the LDS tile in the class's widest storage format
     __shared__ __align__(16) unsigned char lds[CLASS == 2 ? 9 * kPool3EN * 4 : 9 * kPoolEN * (CLASS ? 8 : 4)];
     __shared__ double part[kBlock2 / 64][kRingWidth];
-    __shared__ double outl[3 * kPoolTileH];                   // convective outlet (pool_tile)
+    // convective outlet records: pool_tile's 3 x kPoolTileH, pool_tile3's 3 x (2 kPool3H + 2) (T)
+    __shared__ double outl[3 * (2 * kPool3H + 2)];
     const int n = *ntiles;
     const TileRef tr = tiles[blockIdx.x];                     // the table spans the grid
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
@@ -488,14 +531,14 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     if (pool_class(d.storage, d.conv) != CLASS) return;
     const int k = d.target - done < nsteps ? int(d.target - done) : nsteps;
     if constexpr (CLASS == 2) {
-        if (pool3_inner(d, tr.tile)) pool_tile3<kF32, true>(d, tr.tile, done, k, lds, part, status);
-        else pool_tile3<kF32, false>(d, tr.tile, done, k, lds, part, status);
+        if (pool3_inner(d, tr.tile)) pool_tile3<kF32, true, false>(d, tr.tile, done, k, lds, part, outl, status);
+        else if (d.conv) pool_tile3<kF32, false, true>(d, tr.tile, done, k, lds, part, outl, status);
+        else pool_tile3<kF32, false, false>(d, tr.tile, done, k, lds, part, outl, status);
     } else if constexpr (CLASS == 1) {
         if (d.storage == kF64) pool_tile2<kF64>(d, tr.tile, done, k, lds, part, outl, status);
         else pool_tile2<kF32D>(d, tr.tile, done, k, lds, part, outl, status);
     } else {
         switch (d.storage) {
-        case kF32: pool_tile<kF32, true>(d, tr.tile, done, k, lds, part, outl, status); break;   // outlet only
         case kF16S: pool_tile2<kF16S>(d, tr.tile, done, k, lds, part, outl, status); break;
         case kF16SR: pool_tile2<kF16SR>(d, tr.tile, done, k, lds, part, outl, status); break;
         case kBF16SR: pool_tile2<kBF16SR>(d, tr.tile, done, k, lds, part, outl, status); break;

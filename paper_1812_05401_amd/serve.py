@@ -137,9 +137,10 @@ def cap_sweep(capacity_glups, loads=(1.2, 0.7), caps=(0, 1_000_000, 2_000_000, 4
 
 
 def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30,
-                steps_per_launch=SERVING_REPLAY_STEPS):
+                steps_per_launch=SERVING_REPLAY_STEPS, outlet="outflow"):
     """Throughput of a fixed batch: n square requests of one grid (the serving stream's geometry
-    draws, all `steps` long, in `storage`) submitted at once to a pool without an admission cap,
+    draws, all `steps` long, in `storage`, with the zero-gradient outflow or, outlet="convective",
+    the convective outlet) submitted at once to a pool without an admission cap,
     timed after the first graph replay (which admits them);
     the same requests through the single-simulation API without reductions, one at a time (each
     finished before the next starts), and all at once, each simulation on a stream of its own.
@@ -149,8 +150,12 @@ def fixed_batch(n, grid, steps, storage="f32", budget_bytes=8 << 30,
     import torch
     from . import inputs as I
     reqs = I.serving_requests(n=n, nmin=grid, nmax=grid, steps_range=(steps, steps))
+    if outlet not in ("outflow", "convective"):
+        raise ValueError(f"unknown outlet {outlet!r}")
     for r in reqs:
         r.case.storage = storage
+        if outlet == "convective":
+            r.case.bc = I.CHANNEL_CONVECTIVE
     lups = sum(r.case.nodes * r.case.steps for r in reqs)
     if steps <= steps_per_launch:
         raise ValueError("the batch must run longer than one graph replay")
@@ -217,8 +222,9 @@ def main():
     ap.add_argument("--loads", default="1.2,0.7")
     ap.add_argument("--caps", default="0,1000000,2000000,4000000")
     ap.add_argument("--fifo", action="store_true", help="also run each load one request at a time")
-    ap.add_argument("--batch", default="", metavar="N:GRID:STEPS[:STORAGE],...",
-                    help="fixed batches through the pool against one at a time, e.g. 24:704:2000")
+    ap.add_argument("--batch", default="", metavar="N:GRID:STEPS[:STORAGE[:OUTLET]],...",
+                    help="fixed batches through the pool against one at a time, e.g. 24:704:2000 "
+                         "or 8:2048:1152:f32:convective")
     args = ap.parse_args()
     if not args.cap_sweep and not args.batch:
         ap.error("nothing to do (try --cap-sweep or --batch)")
@@ -229,8 +235,9 @@ def main():
         f = spec.split(":")
         n, grid, steps = int(f[0]), int(f[1]), int(f[2])
         storage = f[3] if len(f) > 3 else "f32"
-        pool_g, single_g, streams_g, nfail = fixed_batch(n, grid, steps, storage)
-        print(f"batch {n} x {grid}^2 {storage} {steps} steps: pool {pool_g:.1f} GLUPS, "
+        outlet = f[4] if len(f) > 4 else "outflow"
+        pool_g, single_g, streams_g, nfail = fixed_batch(n, grid, steps, storage, outlet=outlet)
+        print(f"batch {n} x {grid}^2 {storage} {outlet} {steps} steps: pool {pool_g:.1f} GLUPS, "
               f"one at a time {single_g:.1f}, concurrent streams {streams_g:.1f} "
               f"({nfail} failed in both)", flush=True)
     if not args.cap_sweep:

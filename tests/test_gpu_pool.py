@@ -288,13 +288,14 @@ def convective_requests(seed, storages, steps):
 
 @pytest.mark.parametrize("spl", [1, 7, 64])
 def test_convective_outlet_matches_the_single_simulation_bitwise(gpu, spl):
-    """Requests with a convective outlet take pairs of steps per launch in the pool (binary32 too:
-    the outlet keeps it off the three-step tiles), the outlet's recorded values following the
-    population buffers.  Over step counts of both parities and the storage formats, alone and in
-    a mix with outlet-free requests, the fields are bitwise those of the single-simulation path."""
+    """Requests with a convective outlet in the pool: binary32 takes three steps per launch on its
+    14-row tiles, the outlet's records passed from phase to phase in LDS; the other formats take
+    pairs of steps; the records in memory follow the population buffers.  Over step counts of
+    every residue modulo 2 and 3 and the storage formats, alone and in a mix with outlet-free
+    requests, the fields are bitwise those of the single-simulation path."""
     B = gpu
-    conv = convective_requests(17, ("f32", "f64", "f16s", "f32d", "bf16sr", "f16sr"),
-                               (151, 200, 97, 64, 33, 101))
+    conv = convective_requests(17, ("f32", "f64", "f16s", "f32d", "bf16sr", "f16sr", "f32", "f32"),
+                               (151, 200, 97, 64, 33, 101, 200, 96))
     plain = small_requests(seed=19, n=3, storage="f32")
     res, _ = run(B.Pool, conv + plain, 1 << 30, spl=spl)
     alone = {k: run(B.Pool, [c], 1 << 30, spl=spl)[0][0] for k, c in enumerate(conv[:2])}
