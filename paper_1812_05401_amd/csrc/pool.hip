@@ -516,8 +516,10 @@ __global__ __launch_bounds__(kBlock2) void pool_step_kernel(PoolSim *sims, const
     // the LDS tile in the class's widest storage format
     __shared__ __align__(16) unsigned char lds[CLASS == 2 ? 9 * kPool3EN * 4 : 9 * kPoolEN * (CLASS ? 8 : 4)];
     __shared__ double part[kBlock2 / 64][kRingWidth];
-    // convective outlet records: pool_tile's 3 x kPoolTileH, pool_tile3's 3 x (2 kPool3H + 2) (T)
-    __shared__ double outl[3 * (2 * kPool3H + 2)];
+    // convective outlet records: pool_tile's 3 x kPoolTileH values of T, pool_tile3's
+    // 3 x (2 kPool3H + 2) binary32 values
+    constexpr int kOutl = CLASS == 2 ? (3 * (2 * kPool3H + 2) + 1) / 2 : 3 * kPoolTileH;
+    __shared__ double outl[kOutl];
     const int n = *ntiles;
     const TileRef tr = tiles[blockIdx.x];                     // the table spans the grid
     if ((int)blockIdx.x >= n) return;                         // uniform over the workgroup
