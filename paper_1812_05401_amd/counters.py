@@ -30,13 +30,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("kernels.hip", "lattice.hpp", "kernels.hpp", "runtime.hip")
 
 
-def source_digest():
-    """Digest of the sources the step kernels are built from: a counter summary taken on other
-    sources is not used."""
+def source_digest(csrc=None):
+    """Digest of the code the step kernels are built from (the sources in csrc, by default the
+    package's): a counter summary taken on other code is not used.  Comments and the layout of
+    whitespace are left out, so that an edit of a comment does not discard a summary."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc or os.path.join(HERE, "csrc"), f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -93,3 +93,22 @@ def test_cli_writes_the_table_bench_reads(tmp_path, monkeypatch):
 def test_a_missing_database_is_an_error(tmp_path):
     with pytest.raises(FileNotFoundError):
         C.dispatch_values(str(tmp_path))
+
+
+def test_source_digest_ignores_comments_and_layout(tmp_path):
+    """A counter summary stays valid across an edit of a comment or of whitespace, not across an
+    edit of code."""
+    import shutil
+    src = os.path.join(os.path.dirname(C.__file__), "csrc")
+    for f in C.KERNEL_SOURCES:
+        shutil.copy(os.path.join(src, f), tmp_path / f)
+    base = C.source_digest(str(tmp_path))
+    assert base == C.source_digest()
+    k = tmp_path / "kernels.hpp"
+    text = k.read_text()
+    k.write_text(text.replace("//", "//  (edited)", 1) + "\n/* a block\n   comment */\n")
+    assert C.source_digest(str(tmp_path)) == base
+    k.write_text(text.replace(";", ";\n\n    ", 1))
+    assert C.source_digest(str(tmp_path)) == base
+    k.write_text(text + "\nstatic const int vplbm_digest_probe = 1;\n")
+    assert C.source_digest(str(tmp_path)) != base
