@@ -432,6 +432,13 @@ __device__ __forceinline__ Macro<T> moments(const T h[9], bool solid, T usx, T u
 
 // ---- collision -----------------------------------------------------------------------------------
 
+// a * b + c, rounded once.  A sum of two products is written with its fused product explicit: left
+// to the compiler's contraction, either product may be fused, and the choice can differ between
+// kernels that inline the same code, which would break their bitwise agreement.
+template <typename T> __device__ __forceinline__ T fmadd(T a, T b, T c);
+template <> __device__ __forceinline__ float fmadd<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fmadd<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // One opposite pair (a, abar) of shifted populations with lattice weight w, c = xi_a . u and
 // xf = xi_a . f; q = -1.5 |u|^2.  FORCED = false drops the forcing terms, which vanish at fluid
 // nodes (f = 0 there): the same result, without their arithmetic.
@@ -461,8 +468,8 @@ template <bool FORCED, typename T>
 __device__ __forceinline__ void collide(T h[9], const Macro<T> &m, T sp, T sm, T kp, T km)
 {
     const T ux = m.ux, uy = m.uy, rho = m.rho, drho = m.drho;
-    const T q = T(-1.5) * (ux * ux + uy * uy);
-    const T ufp = FORCED ? ux * m.fx + uy * m.fy : T(0);
+    const T q = T(-1.5) * fmadd(ux, ux, uy * uy);
+    const T ufp = FORCED ? fmadd(ux, m.fx, uy * m.fy) : T(0);
     {
         T heq0 = W<T>::rest * (drho + rho * q);
         h[0] = h[0] - sp * (h[0] - heq0);
